@@ -1,0 +1,29 @@
+"""Compiles the C oracle into oracle/liboracle_star.so with the host compiler.
+
+The oracle is test infrastructure; building it is part of building the
+checker, not of the product path.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "star_oracle.c")
+OUT = os.path.join(HERE, "liboracle_star.so")
+
+
+def build(verbose: bool = False) -> str:
+    cc = os.environ.get("CC", "gcc")
+    tmp = OUT + ".tmp"
+    cmd = [cc, "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", SRC, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
