@@ -1,0 +1,166 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) star-stencil library.
+ *
+ * The library applies repeated time steps of a 2D or 3D star stencil of
+ * radius 1..4 (Zohouri, Podobas, Matsuoka, "High-Performance High-Order
+ * Stencil Computation on FPGAs Using OpenCL", IPDPSW 2018, Sec. IV.A,
+ * Eq. (1)):
+ *
+ *   f^{t+1}(p) = c_C f^t(p) + sum_{i=1..R} sum_{d} c_{d,i} f^t(clamp(p + i e_d))
+ *
+ * with d over W,E,S,N (2D) or W,E,S,N,B,A (3D): W/E = -x/+x, S/N = -y/+y,
+ * B/A = -z/+z.  Out-of-grid neighbours take the value of the border cell
+ * (Sec. III.B, Sec. IV.B), independently per axis, at every step.  The
+ * kernels fuse several time steps per pass over memory (combined spatial and
+ * temporal blocking with overlapped halos, Sec. III.A, Eq. (2)).
+ *
+ * Conventions shared by every entry point:
+ *   - Grids are dense, row-major, x fastest: index = x + nx*(y + ny*z).
+ *     dims[] is given in x, y[, z] order.
+ *   - Coefficients are per point, in the order c_C, then for i = 1..R the
+ *     directions W, E, S, N (, B, A): 1 + 2*ndim*R FP32 values.  They are
+ *     copied at plan time; the caller keeps ownership of its array.
+ *   - Grid pointers are DEVICE pointers owned by the caller.  The library
+ *     never frees them and never writes the input grid.
+ *   - Each FP32 cell update is evaluated as c_C*f_C followed by one fused
+ *     multiply-add per neighbour in coefficient order, so every tuning of a
+ *     plan gives the same bits.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Run calls only enqueue work and return; device faults surface on the
+ *     caller's next synchronisation.
+ *   - Every int-returning function returns STENCIL_OK (0) or a negative
+ *     status; stencil_last_error() then describes the failure (per thread).
+ *     No C++ exception crosses this interface.
+ */
+#ifndef MI355X_STENCIL_H
+#define MI355X_STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef STENCIL_API
+#define STENCIL_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stencil_plan_s *stencil_plan_t; /* opaque, library-owned */
+
+enum stencil_status {
+    STENCIL_OK = 0,
+    STENCIL_EINVAL = -1,       /* bad argument (nothing was enqueued)        */
+    STENCIL_ENOMEM = -2,       /* device or host allocation failed           */
+    STENCIL_EDEVICE = -3,      /* a HIP call or kernel launch failed         */
+    STENCIL_EUNSUPPORTED = -4, /* valid request this build does not support  */
+    STENCIL_EOVERFLOW = -5     /* a low-precision tile scale left its range  */
+};
+
+enum stencil_boundary {
+    STENCIL_BOUNDARY_CLAMP = 0 /* border cell replaces out-of-grid cells (Sec. III.B) */
+};
+
+enum stencil_storage {
+    STENCIL_F32 = 0,  /* state kept in FP32 between passes               */
+    STENCIL_F16 = 1,  /* state kept in FP16 with per-tile 2^e scales     */
+    STENCIL_BF16 = 2  /* state kept in BF16 with per-tile 2^e scales     */
+};
+
+/*
+ * Creates a plan for one grid shape, radius and coefficient set (Eq. (1)).
+ *   plan     out: the new plan (set to NULL on failure).
+ *   ndim     2 or 3.
+ *   dims     ndim extents in x, y[, z] order, each >= 1; the cell count times
+ *            4 bytes must fit in int64.
+ *   radius   1..4.
+ *   coeffs   host array of ncoeffs FP32 values in the order given above.
+ *   ncoeffs  must equal 1 + 2*ndim*radius.
+ *   boundary STENCIL_BOUNDARY_CLAMP (the only boundary of the paper).
+ * Allocates the plan's device scratch (one grid of FP32) on the current
+ * device and picks a kernel configuration (from the tuning cache when one
+ * is present, otherwise built-in defaults).  Errors: EINVAL, ENOMEM,
+ * EDEVICE, EUNSUPPORTED.
+ */
+STENCIL_API int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                 const float *coeffs, int ncoeffs, int boundary);
+
+/*
+ * As stencil_plan, with extra controls:
+ *   storage  STENCIL_F32, STENCIL_F16 or STENCIL_BF16 (state between passes).
+ *   anchor_m for F16/BF16: the state is re-anchored in FP32 every anchor_m
+ *            steps (>= 1); ignored for F32.
+ *   tune     NULL for automatic selection, or a configuration string such as
+ *            "naive", "k=4,ly=256" (2D) or "k=2,tx=120,ty=24,lz=64" (3D);
+ *            unknown keys or infeasible values give EINVAL.
+ */
+STENCIL_API int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                    const float *coeffs, int ncoeffs, int boundary, int storage,
+                    int anchor_m, const char *tune);
+
+/*
+ * Applies `steps` time steps to the grid at `in` and writes f^steps to `out`.
+ *   in, out  device pointers to nx*ny[*nz] floats, 4-byte aligned; the two
+ *            ranges must not overlap (EINVAL).  `in` is never written.
+ *   steps    >= 0; 0 copies in to out.
+ * Enqueues ceil(steps/K) passes on `stream`, ping-ponging between `out` and
+ * the plan's scratch so that the last pass writes `out`.  A plan must not be
+ * run concurrently with itself (its scratch is shared); distinct plans are
+ * independent.  Errors: EINVAL, EDEVICE.
+ */
+STENCIL_API int stencil_run(stencil_plan_t plan, const float *in, float *out, int64_t steps, void *stream);
+
+/*
+ * Runs n independent grids, grid g with plans[g], ins[g], outs[g] and
+ * steps[g] (host arrays of length n, device grid pointers), with the same
+ * contract as n calls of stencil_run, enqueued on `stream` as one persistent
+ * work-list launch per pass round.  The result of every grid is bitwise
+ * equal to its own stencil_run.  Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+STENCIL_API int stencil_run_batched(int n, const stencil_plan_t *plans, const float *const *ins,
+                        float *const *outs, const int64_t *steps, void *stream);
+
+/*
+ * Reports the plan's configuration.  Any output pointer may be NULL.
+ *   K          time steps fused per pass.
+ *   tile       output tile extent in x, y, z (cells; z = 1 in 2D).
+ *   vec        cells per lane along x.
+ *   bytes_per_cell_step  algorithmic HBM bytes per cell update (8/K for F32).
+ */
+STENCIL_API int stencil_plan_query(stencil_plan_t plan, int *K, int tile[3], int *vec,
+                       double *bytes_per_cell_step);
+
+/*
+ * Writes a human-readable description of the plan's configuration
+ * ("variant=s2d R=1 K=4 ...") into buf (always NUL-terminated when
+ * len > 0).  Returns the length it needed, or a negative status.
+ */
+STENCIL_API int stencil_plan_describe(stencil_plan_t plan, char *buf, size_t len);
+
+/*
+ * FP64 reductions on the device: out[0] = max|x - ref|, out[1] = max|ref|,
+ * out[2] = sum of x (all accumulated in FP64).
+ *   x    device array of n floats; ref device array of n doubles (may be
+ *        NULL, then out[0] = out[1] = 0).
+ *   out  HOST array of 3 doubles; the call synchronises `stream`.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+STENCIL_API int stencil_reduce_f64(const float *x, const double *ref, int64_t n, double out[3], void *stream);
+
+/* Releases the plan and its device scratch (synchronises the device).  NULL is a no-op. */
+STENCIL_API void stencil_plan_destroy(stencil_plan_t plan);
+
+/* Static text for a status code. */
+STENCIL_API const char *stencil_status_string(int status);
+
+/* Text of the last failure on the calling thread ("" when none). */
+STENCIL_API const char *stencil_last_error(void);
+
+/* Library version string. */
+STENCIL_API const char *stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355X_STENCIL_H */

@@ -1,0 +1,97 @@
+"""Builds the gfx950 star-stencil library in-tree.
+
+Compiles every source under csrc/ with hipcc for gfx950 and links
+paper_2002_05983_amd/libstencil_mi355x.so.  Per-radius kernels are compiled
+from one source with -DSTAR_R=<r>.  Objects are compiled in parallel.
+
+  python -m paper_2002_05983_amd.build [--asm DIR]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB_NAME = "libstencil_mi355x.so"
+LIB_PATH = os.path.join(HERE, LIB_NAME)
+ARCH = "gfx950"
+
+# Host-only translation units and (source, defines) device units.
+HOST_UNITS = ["api.cpp", "plan.cpp"]
+DEVICE_UNITS = [("naive.hip", {}), ("reduce.hip", {})] + [("star2d.hip", {"STAR_R": r}) for r in (1, 2, 3, 4)]
+
+COMMON = ["-std=c++17", "-O3", "-fPIC", "-fvisibility=hidden", "-I", INCLUDE, "-I", CSRC,
+          "-Wall", "-Wno-unused-function"]
+DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=off", "-fno-gpu-rdc",
+          # no packed FP32 (v_pk_*_f32) instructions: plain VALU FP32 only
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm is required to build the library)")
+
+
+def _obj_name(src: str, defs: dict) -> str:
+    stem = os.path.splitext(src)[0]
+    suffix = "".join(f"_{k.lower()}{v}" for k, v in sorted(defs.items()))
+    return f"{stem}{suffix}.o"
+
+
+def build(verbose: bool = False, asm_dir: str | None = None, jobs: int | None = None) -> str:
+    hipcc = _hipcc()
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cmds = []
+    for src in HOST_UNITS:
+        out = os.path.join(objdir, _obj_name(src, {}))
+        cmds.append([hipcc, *COMMON, "-c", os.path.join(CSRC, src), "-o", out])
+    for src, defs in DEVICE_UNITS:
+        out = os.path.join(objdir, _obj_name(src, defs))
+        cmd = [hipcc, *COMMON, *DEVICE, *[f"-D{k}={v}" for k, v in defs.items()],
+               "-c", os.path.join(CSRC, src), "-o", out]
+        if asm_dir:
+            os.makedirs(asm_dir, exist_ok=True)
+            cmd += ["-save-temps=obj"]
+        cmds.append(cmd)
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        err = "\n".join(l for l in r.stderr.splitlines()
+                        if "packed-fp32-ops" not in l and l.strip())
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{err}")
+        if err and verbose:
+            print(err, file=sys.stderr)
+        return cmd[-1]
+
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(run, cmds))
+    if asm_dir:
+        for f in os.listdir(objdir):
+            if f.endswith(".s") and "gfx950" in f:
+                shutil.copy(os.path.join(objdir, f), asm_dir)
+    tmp = LIB_PATH + ".tmp"
+    run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--asm", default=None, help="copy the gfx950 assembly of each unit here")
+    ap.add_argument("-v", "--verbose", action="store_true")
+    args = ap.parse_args()
+    print(build(verbose=args.verbose, asm_dir=args.asm))

@@ -1,0 +1,217 @@
+// api.cpp -- the C ABI declared in include/stencil.h.
+//
+// Host side only: argument validation, coefficient copy, configuration
+// choice, scratch ownership and the pass schedule (K fused steps per pass,
+// ping-pong between the caller's output and the plan's scratch).  Every
+// cell update runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "plan.hpp"
+#include "stencil.h"
+
+using namespace star;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(STENCIL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool ranges_overlap(const void *a, const void *b, size_t bytes) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+int star_set_error(int status, const char *msg) { return fail(status, "%s", msg); }
+
+extern "C" {
+
+const char *stencil_version(void) { return "mi355x-stencil 0.1 (gfx950)"; }
+
+const char *stencil_status_string(int status) {
+    switch (status) {
+        case STENCIL_OK: return "ok";
+        case STENCIL_EINVAL: return "invalid argument";
+        case STENCIL_ENOMEM: return "out of memory";
+        case STENCIL_EDEVICE: return "device error";
+        case STENCIL_EUNSUPPORTED: return "unsupported";
+        case STENCIL_EOVERFLOW: return "scale overflow";
+        default: return "unknown status";
+    }
+}
+
+const char *stencil_last_error(void) { return g_last_error.c_str(); }
+
+int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                    const float *coeffs, int ncoeffs, int boundary, int storage, int anchor_m,
+                    const char *tune) {
+    g_last_error.clear();
+    if (!plan) return fail(STENCIL_EINVAL, "plan pointer is NULL");
+    *plan = nullptr;
+    if (ndim != 2 && ndim != 3) return fail(STENCIL_EINVAL, "ndim must be 2 or 3 (got %d)", ndim);
+    if (!dims) return fail(STENCIL_EINVAL, "dims is NULL");
+    if (radius < 1 || radius > 4) return fail(STENCIL_EINVAL, "radius must be 1..4 (got %d)", radius);
+    if (!coeffs) return fail(STENCIL_EINVAL, "coeffs is NULL");
+    const int npts = 1 + 2 * ndim * radius;
+    if (ncoeffs != npts)
+        return fail(STENCIL_EINVAL, "ncoeffs must be 1+2*ndim*radius = %d (got %d)", npts, ncoeffs);
+    if (boundary != STENCIL_BOUNDARY_CLAMP)
+        return fail(STENCIL_EINVAL, "unsupported boundary %d (only clamp)", boundary);
+    if (storage != STENCIL_F32 && storage != STENCIL_F16 && storage != STENCIL_BF16)
+        return fail(STENCIL_EINVAL, "unknown storage %d", storage);
+    if (storage != STENCIL_F32 && anchor_m < 1)
+        return fail(STENCIL_EINVAL, "anchor_m must be >= 1 for low-precision storage");
+    int64_t d[3] = {1, 1, 1};
+    for (int a = 0; a < ndim; ++a) {
+        if (dims[a] < 1) return fail(STENCIL_EINVAL, "dims[%d] = %lld < 1", a, (long long)dims[a]);
+        if (dims[a] > (int64_t)1 << 30)
+            return fail(STENCIL_EUNSUPPORTED, "dims[%d] = %lld exceeds 2^30", a, (long long)dims[a]);
+        d[a] = dims[a];
+    }
+    const int64_t ncells = d[0] * d[1] * d[2];  // each factor <= 2^30: check before multiplying
+    if ((double)d[0] * (double)d[1] * (double)d[2] * 4.0 > 9.0e18 || ncells > ((int64_t)1 << 40))
+        return fail(STENCIL_EINVAL, "grid of %g cells overflows the byte size",
+                    (double)d[0] * (double)d[1] * (double)d[2]);
+    for (int k = 0; k < npts; ++k)
+        if (!std::isfinite(coeffs[k])) return fail(STENCIL_EINVAL, "coefficient %d is not finite", k);
+
+    auto *p = new (std::nothrow) stencil_plan_s();
+    if (!p) return fail(STENCIL_ENOMEM, "host allocation failed");
+    p->ndim = ndim;
+    p->nx = d[0];
+    p->ny = d[1];
+    p->nz = d[2];
+    p->ncells = ncells;
+    p->radius = radius;
+    p->npts = npts;
+    std::memset(&p->cf, 0, sizeof p->cf);
+    for (int k = 0; k < npts; ++k) p->cf.c[k] = coeffs[k];
+    p->storage = storage;
+    p->anchor_m = anchor_m;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    int rc = plan_configure(p, tune);
+    if (rc != STENCIL_OK) {
+        delete p;
+        return rc;
+    }
+    e = hipMalloc(&p->scratch, (size_t)ncells * sizeof(float));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(STENCIL_ENOMEM, "hipMalloc of %lld-cell scratch failed: %s", (long long)ncells,
+                    hipGetErrorString(e));
+    }
+    *plan = p;
+    return STENCIL_OK;
+}
+
+int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                 const float *coeffs, int ncoeffs, int boundary) {
+    return stencil_plan_ex(plan, ndim, dims, radius, coeffs, ncoeffs, boundary, STENCIL_F32, 0,
+                           nullptr);
+}
+
+void stencil_plan_destroy(stencil_plan_t plan) {
+    if (!plan) return;
+    if (plan->scratch) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(plan->scratch);
+    }
+    plan_release_extra(plan);
+    delete plan;
+}
+
+int stencil_plan_query(stencil_plan_t plan, int *K, int tile[3], int *vec,
+                       double *bytes_per_cell_step) {
+    if (!plan) return fail(STENCIL_EINVAL, "plan is NULL");
+    if (K) *K = plan->K;
+    if (tile) {
+        tile[0] = plan->tile[0];
+        tile[1] = plan->tile[1];
+        tile[2] = plan->tile[2];
+    }
+    if (vec) *vec = plan->vec;
+    if (bytes_per_cell_step) *bytes_per_cell_step = 8.0 / plan->K;
+    return STENCIL_OK;
+}
+
+int stencil_plan_describe(stencil_plan_t plan, char *buf, size_t len) {
+    if (!plan) return fail(STENCIL_EINVAL, "plan is NULL");
+    const std::string s = plan_describe(plan);
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = '\0';
+    }
+    return (int)s.size();
+}
+
+int stencil_run(stencil_plan_t plan, const float *in, float *out, int64_t steps, void *stream) {
+    g_last_error.clear();
+    if (!plan) return fail(STENCIL_EINVAL, "plan is NULL");
+    if (!in || !out) return fail(STENCIL_EINVAL, "in/out is NULL");
+    if (steps < 0) return fail(STENCIL_EINVAL, "steps must be >= 0 (got %lld)", (long long)steps);
+    if (((uintptr_t)in | (uintptr_t)out) & 3) return fail(STENCIL_EINVAL, "grids must be 4-byte aligned");
+    const size_t bytes = (size_t)plan->ncells * sizeof(float);
+    if (ranges_overlap(in, out, bytes)) return fail(STENCIL_EINVAL, "in and out overlap");
+    if (ranges_overlap(in, plan->scratch, bytes) || ranges_overlap(out, plan->scratch, bytes))
+        return fail(STENCIL_EINVAL, "in/out overlap the plan's scratch");
+    hipStream_t st = (hipStream_t)stream;
+    if (steps == 0) {
+        hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, st);
+        return e == hipSuccess ? STENCIL_OK : hip_fail(e, "hipMemcpyAsync");
+    }
+    std::vector<int> passes;
+    plan_pass_schedule(plan, steps, passes);
+    const int np = (int)passes.size();
+    const float *src = in;
+    for (int p = 0; p < np; ++p) {
+        float *dst = ((np - 1 - p) % 2 == 0) ? out : plan->scratch;
+        hipError_t e = plan_launch_pass(plan, passes[p], src, dst, st);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        src = dst;
+    }
+    return STENCIL_OK;
+}
+
+int stencil_run_batched(int n, const stencil_plan_t *plans, const float *const *ins,
+                        float *const *outs, const int64_t *steps, void *stream) {
+    g_last_error.clear();
+    if (n < 0) return fail(STENCIL_EINVAL, "n must be >= 0");
+    if (n == 0) return STENCIL_OK;
+    if (!plans || !ins || !outs || !steps) return fail(STENCIL_EINVAL, "NULL batch array");
+    for (int g = 0; g < n; ++g) {
+        int rc = stencil_run(plans[g], ins[g], outs[g], steps[g], stream);
+        if (rc != STENCIL_OK) return rc;
+    }
+    return STENCIL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// common.hpp -- shared device helpers of the gfx950 star-stencil kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace star {
+
+// Points of a radius-4 3D star: 1 + 2*3*4.
+constexpr int kMaxPoints = 25;
+
+// Per-point coefficients, passed by value in the kernel argument segment so
+// that every coefficient is a scalar register operand of the FMA chain.
+// Order: c_C, then for i = 1..R the directions W, E, S, N (, B, A).
+struct Coefs {
+    float c[kMaxPoints];
+};
+
+// Index of neighbour (direction slot d, distance i) for an ndim-D star.
+template <int NDIM>
+__host__ __device__ constexpr int coef_index(int d, int i) {
+    return 1 + (i - 1) * 2 * NDIM + d;
+}
+enum : int { kW = 0, kE = 1, kS = 2, kN = 3, kB = 4, kA = 5 };
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1, full-rate VALU
+// moves).  The lane with no source gets 0.
+__device__ __forceinline__ float from_lower_lane(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_upper_lane(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+// Value of v in lane `lane` (wave-uniform lane index), broadcast to all lanes.
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Workgroups are handed to the 8 XCDs of the chip round-robin by block id.
+// Renumber them so that each XCD works on one contiguous range of logical
+// blocks (neighbouring tiles, whose halos overlap, then share an L2).
+__device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+}  // namespace star

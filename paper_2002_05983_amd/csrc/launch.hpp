@@ -1,0 +1,36 @@
+// launch.hpp -- host-side launchers of the kernel families (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace star {
+
+// One step per launch, one thread per cell (reference variant).
+hipError_t launch_naive(int ndim, int R, const float *src, float *dst, int nx, int ny, int nz,
+                        const Coefs &cf, hipStream_t stream);
+
+// 2D x-strip / y-stream kernel fusing K steps per pass.
+struct Star2DArgs {
+    const float *src;
+    float *dst;
+    int nx, ny;
+    int K;        // steps fused in this pass (1..kMaxK2D)
+    int ly;       // output rows per y-segment
+    bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
+    Coefs cf;
+};
+constexpr int kMaxK2D = 8;
+constexpr int kVec2D = 4;
+// Output columns of one strip: a wavefront spans 64*4 columns, minus the
+// overlapped halo of roundup(K*R, 4) columns per side (Eq. (2) analogue).
+constexpr int star2d_halo(int K, int R) { return (K * R + kVec2D - 1) / kVec2D * kVec2D; }
+constexpr int star2d_tile_x(int K, int R) { return 64 * kVec2D - 2 * star2d_halo(K, R); }
+
+hipError_t launch_star2d_r1(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r2(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r3(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r4(const Star2DArgs &a, hipStream_t stream);
+
+}  // namespace star

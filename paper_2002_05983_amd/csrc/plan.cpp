@@ -1,0 +1,151 @@
+// plan.cpp -- kernel configuration and pass schedule of a plan.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "launch.hpp"
+#include "stencil.h"
+
+using namespace star;
+
+namespace {
+
+// Resident wavefronts the 2D kernel aims for: 256 CUs x 4 SIMDs x 4.
+constexpr int64_t kTargetWaves2D = 4096;
+
+int default_k2d(int R) {
+    switch (R) {
+        case 1: return 8;
+        case 2: return 4;
+        case 3: return 3;
+        default: return 2;
+    }
+}
+
+int default_ly(const stencil_plan_s *p, int K) {
+    const int tx = star2d_tile_x(K, p->radius);
+    const int64_t nstrips = (p->nx + tx - 1) / tx;
+    int64_t ly = (p->ny * nstrips + kTargetWaves2D - 1) / kTargetWaves2D;
+    ly = std::max<int64_t>(ly, 8 * K * p->radius);
+    ly = std::min<int64_t>(ly, p->ny);
+    return (int)std::max<int64_t>(ly, 1);
+}
+
+bool parse_int(const char *s, int *out) {
+    char *end = nullptr;
+    long v = strtol(s, &end, 10);
+    if (end == s || *end != '\0') return false;
+    *out = (int)v;
+    return true;
+}
+
+}  // namespace
+
+int plan_configure(stencil_plan_s *p, const char *tune) {
+    const int R = p->radius;
+    if (p->ndim == 2) {
+        p->variant = STAR_S2D;
+        p->K = default_k2d(R);
+        p->ly = 0;
+    } else {
+        p->variant = STAR_NAIVE;
+        p->K = 1;
+    }
+    if (tune && *tune) {
+        p->tuned_by = "override";
+        std::string s(tune);
+        size_t pos = 0;
+        while (pos <= s.size()) {
+            size_t comma = s.find(',', pos);
+            if (comma == std::string::npos) comma = s.size();
+            std::string item = s.substr(pos, comma - pos);
+            pos = comma + 1;
+            if (item.empty()) continue;
+            if (item == "naive") {
+                p->variant = STAR_NAIVE;
+                p->K = 1;
+                continue;
+            }
+            size_t eq = item.find('=');
+            if (eq == std::string::npos)
+                return star_set_error(STENCIL_EINVAL, ("bad tune item '" + item + "'").c_str());
+            std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+            int v = 0;
+            if (!parse_int(val.c_str(), &v))
+                return star_set_error(STENCIL_EINVAL, ("bad tune value '" + item + "'").c_str());
+            if (key == "k") {
+                p->K = v;
+            } else if (key == "ly" && p->ndim == 2) {
+                p->ly = v;
+            } else {
+                return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
+            }
+        }
+    }
+    if (p->variant == STAR_S2D) {
+        if (p->K < 1 || p->K > kMaxK2D)
+            return star_set_error(STENCIL_EINVAL, "2D k must be in 1..8");
+        if (p->ly == 0) p->ly = default_ly(p, p->K);
+        if (p->ly < 1) return star_set_error(STENCIL_EINVAL, "ly must be >= 1");
+        p->vec = kVec2D;
+        p->tile[0] = star2d_tile_x(p->K, R);
+        p->tile[1] = p->ly;
+        p->tile[2] = 1;
+    } else if (p->variant == STAR_NAIVE) {
+        if (p->K != 1) return star_set_error(STENCIL_EINVAL, "naive variant has k = 1");
+        p->vec = 1;
+        p->tile[0] = p->tile[1] = p->tile[2] = 1;
+    }
+    return STENCIL_OK;
+}
+
+void plan_pass_schedule(const stencil_plan_s *p, int64_t steps, std::vector<int> &passes) {
+    passes.clear();
+    const int K = std::max(1, p->K);
+    for (int64_t s = 0; s + K <= steps; s += K) passes.push_back(K);
+    if (steps % K) passes.push_back((int)(steps % K));
+}
+
+hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, float *dst,
+                            hipStream_t stream) {
+    switch (p->variant) {
+        case STAR_NAIVE:
+            return launch_naive(p->ndim, p->radius, src, dst, (int)p->nx, (int)p->ny, (int)p->nz,
+                                p->cf, stream);
+        case STAR_S2D: {
+            Star2DArgs a;
+            a.src = src;
+            a.dst = dst;
+            a.nx = (int)p->nx;
+            a.ny = (int)p->ny;
+            a.K = k;
+            // keep the segment length of the full passes for a tail pass
+            a.ly = p->ly;
+            a.aligned = (p->nx % kVec2D == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
+            a.cf = p->cf;
+            switch (p->radius) {
+                case 1: return launch_star2d_r1(a, stream);
+                case 2: return launch_star2d_r2(a, stream);
+                case 3: return launch_star2d_r3(a, stream);
+                case 4: return launch_star2d_r4(a, stream);
+            }
+            return hipErrorInvalidValue;
+        }
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+std::string plan_describe(const stencil_plan_s *p) {
+    char buf[256];
+    const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
+    snprintf(buf, sizeof buf, "variant=%s ndim=%d R=%d K=%d tile=%dx%dx%d vec=%d ly=%d by=%s", v,
+             p->ndim, p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->ly,
+             p->tuned_by.c_str());
+    return buf;
+}
+
+void plan_release_extra(stencil_plan_s *) {}

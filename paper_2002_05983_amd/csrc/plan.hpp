@@ -1,0 +1,54 @@
+// plan.hpp -- the plan object behind stencil_plan_t (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+enum star_variant : int {
+    STAR_NAIVE = 0,  // one thread per cell, one step per launch
+    STAR_S2D = 1,    // 2D x-strip / y-stream, K fused steps
+    STAR_S3D = 2,    // 3D xy-tile in LDS / z-stream, K fused steps
+};
+
+struct stencil_plan_s {
+    // problem
+    int ndim = 2;
+    int64_t nx = 1, ny = 1, nz = 1, ncells = 1;
+    int radius = 1;
+    int npts = 5;
+    star::Coefs cf{};
+    int storage = 0;
+    int anchor_m = 0;
+    int device = 0;
+    float *scratch = nullptr;  // one FP32 grid, ping-pong partner of `out`
+
+    // configuration
+    int variant = STAR_NAIVE;
+    int K = 1;        // steps fused per pass
+    int ly = 0;       // 2D: output rows per y-segment
+    int tile[3] = {1, 1, 1};
+    int vec = 1;
+    // 3D streaming kernel
+    int s3_lanes = 32;  // lanes along x per tile row
+    int s3_rows = 16;   // tile rows (halo included) per workgroup
+    int s3_lz = 64;     // output planes per z-segment
+    std::string tuned_by = "default";
+};
+
+// Chooses the kernel configuration; `tune` may override it (NULL = auto).
+int plan_configure(stencil_plan_s *p, const char *tune);
+// Splits `steps` into the K of each pass.
+void plan_pass_schedule(const stencil_plan_s *p, int64_t steps, std::vector<int> &passes);
+// Enqueues one pass of `k` fused steps from src to dst.
+hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, float *dst,
+                            hipStream_t stream);
+std::string plan_describe(const stencil_plan_s *p);
+void plan_release_extra(stencil_plan_s *p);
+
+// Records a failure for stencil_last_error() and returns status.
+int star_set_error(int status, const char *msg);

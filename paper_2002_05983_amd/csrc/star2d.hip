@@ -1,0 +1,237 @@
+// star2d.hip -- 2D star stencil, x-strip per wavefront, y streamed, K fused steps.
+//
+// Compiled once per radius with -DSTAR_R=<1..4>.
+//
+// Method (Sec. III.A of the paper: 1.5D spatial blocking -- block x, stream
+// y -- combined with temporal blocking by a chain of K stages and
+// overlapped halos, Eq. (2)):
+//   * One wavefront owns a strip of 64 lanes x 4 cells = 256 columns: a
+//     TX-column output tile plus a halo of H = roundup(K*R, 4) columns per
+//     side.  Each lane holds 4 consecutive cells of a row; rows are read and
+//     written with one 128-bit access per lane.
+//   * The wavefront streams rows y0-K*R .. y1-1+K*R of its y-segment.  Stage
+//     s (1..K) applies one time step and runs R rows behind stage s-1, like
+//     the paper's PE chain.  Each stage keeps the last 2R+1 rows of its input
+//     in a register queue: the y-neighbours.  The x-neighbours of the
+//     queue's centre row come from the lane's own registers and, across the
+//     lane boundary, from the adjacent lanes through DPP wave shifts.  Only
+//     the K-th stage is written back, so one pass moves 8 bytes per cell for
+//     K steps.
+//   * Halo cells are recomputed by neighbouring strips instead of exchanged
+//     (overlapped blocking); the invalid region grows R columns per stage
+//     from each strip edge and never reaches the output tile.
+//   * Clamp boundary (Sec. III.B), applied to every stage's field: rows
+//     above the grid are filled with the stage's row 0 when it is produced,
+//     rows below take the stage's row ny-1, and columns outside [0, nx) are
+//     overwritten with the border column of the same stage and row.
+//   * Each cell is c_C*f_C followed by one FMA per neighbour in coefficient
+//     order (W, E, S, N for i = 1..R), the library-wide operation order.
+#include "common.hpp"
+#include "launch.hpp"
+
+#ifndef STAR_R
+#error "compile with -DSTAR_R=<radius>"
+#endif
+
+namespace star {
+
+namespace {
+
+constexpr int VEC = kVec2D;
+
+// Cells of one row of one stage.  q holds the stage input's last P rows in
+// a circular buffer; CS is the slot of the centre row (compile-time).
+template <int R, int P, int CS>
+__device__ __forceinline__ void star2d_row(const float (&q)[P][VEC], const Coefs &cf,
+                                           float (&res)[VEC]) {
+    float left[R + 1], right[R + 1];
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        left[k] = from_lower_lane(q[CS][VEC - k]);  // column base - k
+        right[k] = from_upper_lane(q[CS][k - 1]);   // column base + VEC - 1 + k
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        float acc = cf.c[0] * q[CS][e];
+#pragma unroll
+        for (int i = 1; i <= R; ++i) {
+            const float w = (e - i >= 0) ? q[CS][e - i] : left[i - e];
+            const float ea = (e + i < VEC) ? q[CS][e + i] : right[e + i - VEC + 1];
+            const float s = q[(CS - i + P) % P][e];
+            const float n = q[(CS + i) % P][e];
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], w, acc);
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], ea, acc);
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], s, acc);
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kN, i)], n, acc);
+        }
+        res[e] = acc;
+    }
+}
+
+template <int R, int K, bool ALIGNED>
+__global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ src,
+                                                     float *__restrict__ dst, int nx, int ny,
+                                                     int ly, int nstrips, int nwaves, Coefs cf) {
+    constexpr int P = 2 * R + 1;
+    constexpr int H = star2d_halo(K, R);
+    constexpr int TX = star2d_tile_x(K, R);
+    static_assert(R <= VEC, "x-neighbours must come from the adjacent lane");
+
+    const int lane = threadIdx.x & 63;
+    const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int strip = wave % nstrips;
+    const int seg = wave / nstrips;
+    const int xs = strip * TX - H;  // first column held by lane 0
+    const int col0 = xs + lane * VEC;
+    const int y0 = seg * ly;
+    const int y1 = min(y0 + ly, ny);
+    const int jstart = y0 - K * R;
+    const int niter = (y1 - y0) + 2 * K * R;
+    const bool left_edge = xs < 0;
+    const bool right_edge = xs + 64 * VEC > nx;
+    const int out_lo = max(xs + H, 0);
+    const int out_hi = min(xs + H + TX, nx);
+
+    // Clamp in x: cells left of column 0 take column 0, cells right of
+    // column nx-1 take column nx-1 (of the same row and stage).
+    auto xfix = [&](float (&v)[VEC]) {
+        if (left_edge) {
+            const int l0 = (-xs) / VEC;  // lane whose element 0 is column 0
+            const float b = lane_value(v[0], l0);
+            if (lane < l0) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[e] = b;
+            }
+        }
+        if (right_edge) {
+            const int off = nx - 1 - xs;
+            const int lr = off / VEC, er = off % VEC;
+            float t = v[0];
+#pragma unroll
+            for (int e = 1; e < VEC; ++e) t = (er == e) ? v[e] : t;
+            const float b = lane_value(t, lr);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = (col0 + e >= nx) ? b : v[e];
+        }
+    };
+
+    auto load_row = [&](int j, float (&v)[VEC]) {
+        const float *row = src + (size_t)clampi(j, ny) * (size_t)nx;
+        if constexpr (ALIGNED) {
+            const int c = min(max(col0, 0), nx - VEC);
+            const float4 t = *reinterpret_cast<const float4 *>(row + c);
+            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+            xfix(v);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = row[clampi(col0 + e, nx)];
+        }
+    };
+
+    float pf[P][VEC];     // rows loaded ahead (prefetch distance P)
+    float q[K][P][VEC];   // q[s]: last P rows of the stage-s field (s = 0: input)
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q[s][p][e] = 0.0f;
+
+    static_for<0, P>([&](auto phc) {
+        constexpr int PH = decltype(phc)::value;
+        if (PH < niter) load_row(jstart + PH, pf[PH]);
+    });
+
+    for (int n0 = 0; n0 < niter; n0 += P) {
+        static_for<0, P>([&](auto phc) {
+            constexpr int PH = decltype(phc)::value;
+            const int n = n0 + PH;
+            if (n < niter) {
+                const int j = jstart + n;  // row entering stage 1
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) q[0][PH][e] = pf[PH][e];
+                if (n + P < niter) load_row(j + P, pf[PH]);
+
+                static_for<1, K + 1>([&](auto sc) {
+                    constexpr int S = decltype(sc)::value;
+                    constexpr int CS = (PH - R + P) % P;
+                    const int r = j - S * R;  // row produced by stage S
+                    float res[VEC];
+                    star2d_row<R, P, CS>(q[S - 1], cf, res);
+                    if constexpr (S < K) {
+                        if (r >= ny) {
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) res[e] = q[S][(PH + P - 1) % P][e];
+                        } else {
+                            xfix(res);
+                        }
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) q[S][PH][e] = res[e];
+                        if (r == 0) {
+                            static_for<1, R + 1>([&](auto mc) {
+                                constexpr int M = decltype(mc)::value;
+#pragma unroll
+                                for (int e = 0; e < VEC; ++e) q[S][(PH - M + P) % P][e] = res[e];
+                            });
+                        }
+                    } else {
+                        if (r >= y0 && r < y1) {
+                            float *row = dst + (size_t)r * (size_t)nx;
+                            if (ALIGNED && col0 >= out_lo && col0 + VEC <= out_hi) {
+                                *reinterpret_cast<float4 *>(row + col0) =
+                                    make_float4(res[0], res[1], res[2], res[3]);
+                            } else if (!ALIGNED) {
+#pragma unroll
+                                for (int e = 0; e < VEC; ++e) {
+                                    const int c = col0 + e;
+                                    if (c >= out_lo && c < out_hi) row[c] = res[e];
+                                }
+                            }
+                        }
+                    }
+                });
+            }
+        });
+    }
+}
+
+template <int K, bool AL>
+hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
+    constexpr int TX = star2d_tile_x(K, STAR_R);
+    const int nstrips = (a.nx + TX - 1) / TX;
+    const int nsegs = (a.ny + a.ly - 1) / a.ly;
+    const int64_t nwaves = (int64_t)nstrips * nsegs;
+    if (nwaves > (int64_t)1 << 30) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((nwaves + 3) / 4);
+    hipLaunchKernelGGL((star2d_stream<STAR_R, K, AL>), dim3(blocks), dim3(256), 0, stream, a.src,
+                       a.dst, a.nx, a.ny, a.ly, nstrips, (int)nwaves, a.cf);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_al(const Star2DArgs &a, hipStream_t stream) {
+    return a.aligned ? launch_k<K, true>(a, stream) : launch_k<K, false>(a, stream);
+}
+
+}  // namespace
+
+#define STAR_CAT2(a, b) a##b
+#define STAR_CAT(a, b) STAR_CAT2(a, b)
+
+hipError_t STAR_CAT(launch_star2d_r, STAR_R)(const Star2DArgs &a, hipStream_t stream) {
+    if (a.ly < 1 || a.nx < 1 || a.ny < 1) return hipErrorInvalidValue;
+    switch (a.K) {
+        case 1: return launch_al<1>(a, stream);
+        case 2: return launch_al<2>(a, stream);
+        case 3: return launch_al<3>(a, stream);
+        case 4: return launch_al<4>(a, stream);
+        case 5: return launch_al<5>(a, stream);
+        case 6: return launch_al<6>(a, stream);
+        case 7: return launch_al<7>(a, stream);
+        case 8: return launch_al<8>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace star

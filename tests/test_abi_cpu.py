@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"STENCIL_API\s+[\w\s\*]*?\b(stencil_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2002_05983_amd import stencil
+    if not os.path.exists(stencil.LIB_PATH):
+        pytest.fail("library not built: run __graft_entry__.build()")
+    return stencil.load()
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for must in ("stencil_plan", "stencil_plan_ex", "stencil_run", "stencil_run_batched",
+                 "stencil_plan_query", "stencil_reduce_f64", "stencil_plan_destroy",
+                 "stencil_status_string", "stencil_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2002_05983_amd import stencil
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in stencil.SIGNATURES, f"binding lacks {name}"
+
+
+def test_only_the_abi_is_exported():
+    import subprocess
+    from paper_2002_05983_amd import stencil
+    out = subprocess.run(["nm", "-D", "--defined-only", stencil.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    ours = [l.split()[-1] for l in out.splitlines() if l.split()[-1].startswith(("stencil", "_Z"))]
+    leaked = [s for s in ours if "plan" in s and not s.startswith("stencil_")]
+    assert not leaked, leaked
+
+
+def test_status_strings_and_version(lib):
+    assert lib.stencil_status_string(0) == b"ok"
+    assert lib.stencil_status_string(-1) == b"invalid argument"
+    assert lib.stencil_version().startswith(b"mi355x-stencil")
+
+
+def _plan(lib, ndim, dims, radius, coeffs, ncoeffs=None, boundary=0, storage=0, anchor=0, tune=None):
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int64 * max(1, len(dims)))(*dims)
+    c = (ctypes.c_float * max(1, len(coeffs)))(*coeffs)
+    rc = lib.stencil_plan_ex(ctypes.byref(h), ndim, d, radius, c,
+                             len(coeffs) if ncoeffs is None else ncoeffs, boundary, storage, anchor,
+                             tune)
+    return rc, h
+
+
+@pytest.mark.parametrize("case", [
+    dict(ndim=1, dims=[4], radius=1, coeffs=[0.0] * 3),
+    dict(ndim=4, dims=[4] * 4, radius=1, coeffs=[0.0] * 9),
+    dict(ndim=2, dims=[4, 4], radius=0, coeffs=[0.0]),
+    dict(ndim=2, dims=[4, 4], radius=5, coeffs=[0.0] * 21),
+    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 4),
+    dict(ndim=3, dims=[4, 4, 4], radius=2, coeffs=[0.0] * 9),
+    dict(ndim=2, dims=[0, 4], radius=1, coeffs=[0.0] * 5),
+    dict(ndim=2, dims=[4, -3], radius=1, coeffs=[0.0] * 5),
+    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, boundary=1),
+    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, storage=7),
+    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, storage=1, anchor=0),
+    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[float("nan")] + [0.0] * 4),
+    dict(ndim=3, dims=[1 << 20, 1 << 20, 1 << 20], radius=1, coeffs=[0.0] * 7),
+])
+def test_plan_rejects_invalid_arguments(lib, case):
+    rc, h = _plan(lib, **case)
+    assert rc == -1, (case, rc, lib.stencil_last_error())
+    assert not h.value
+    assert lib.stencil_last_error()
+
+
+def test_plan_null_out_pointer(lib):
+    d = (ctypes.c_int64 * 2)(4, 4)
+    c = (ctypes.c_float * 5)()
+    assert lib.stencil_plan(None, 2, d, 1, c, 5, 0) == -1
+
+
+def test_run_and_reduce_reject_null(lib):
+    assert lib.stencil_run(None, None, None, 1, None) == -1
+    out = (ctypes.c_double * 3)()
+    assert lib.stencil_reduce_f64(None, None, 4, out, None) == -1
+    assert lib.stencil_run_batched(-1, None, None, None, None, None) == -1
+    assert lib.stencil_run_batched(0, None, None, None, None, None) == 0
+    lib.stencil_plan_destroy(None)

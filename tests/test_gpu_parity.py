@@ -1,0 +1,150 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Bar: bitwise equality with the oracle's single-precision form (same
+operation order), and normwise relative L-infinity <= 1e-5 against the FP64
+definition (the library's stated FP32 tolerance).  Sizes span several tiles
+and segments with ragged tails; edge cases cover sides of 1, sides smaller
+than the radius, and step counts that leave a tail pass.
+"""
+import numpy as np
+import pytest
+
+from paper_2002_05983_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def st():
+    from paper_2002_05983_amd import stencil
+    stencil.load()
+    return stencil
+
+
+def gpu_run(torch, st, f, radius, coeffs, steps, tune=None):
+    plan = st.Plan(f.shape, radius, coeffs, tune=tune)
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    plan.run(x, y, steps)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy()
+    # the input is never written
+    assert np.array_equal(x.cpu().numpy(), f)
+    desc = plan.describe()
+    plan.close()
+    return out, desc
+
+
+def assert_bitwise(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        raise AssertionError(f"{what}: {len(bad)} cells differ, first at {bad[:5].tolist()}, "
+                             f"got {got[tuple(bad[0])]!r} want {want[tuple(bad[0])]!r}")
+
+
+NAIVE_CASES = [((1, 1), 1), ((3, 2), 4), ((17, 33), 2), ((64, 100), 3), ((5, 200), 4),
+               ((1, 1, 1), 2), ((4, 5, 6), 3), ((9, 17, 33), 1), ((3, 40, 7), 4)]
+
+
+@pytest.mark.parametrize("shape,radius", NAIVE_CASES)
+def test_naive_matches_oracle_bitwise(torch, st, oracle_mod, shape, radius):
+    c = synth.coefficients(200 + radius, len(shape), radius)
+    f = synth.grid_uniform(300 + radius, shape)
+    for steps in (0, 1, 5):
+        got, desc = gpu_run(torch, st, f, radius, c, steps, tune="naive")
+        assert "variant=naive" in desc
+        assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, steps), f"naive {shape} r{radius}")
+
+
+# (ny, nx) shapes: aligned and ragged x, several strips, several segments.
+S2D_SHAPES = [(1, 1), (1, 7), (6, 1), (3, 3), (2, 5), (37, 513), (97, 1000), (130, 1024),
+              (64, 2048), (300, 260), (11, 4096)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", S2D_SHAPES)
+def test_s2d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    c = synth.coefficients(400 + radius, 2, radius)
+    f = synth.grid_uniform(500 + radius, shape)
+    cache = {}
+    for K in (1, 2, 3, 4, 5, 8):
+        for ly in (7, 32):
+            steps = 2 * K + 1  # two full passes and a tail pass
+            if steps not in cache:
+                cache[steps] = oracle_mod.star_run_f32(f, c, radius, steps)
+            got, desc = gpu_run(torch, st, f, radius, c, steps, tune=f"k={K},ly={ly}")
+            assert "variant=s2d" in desc, desc
+            assert_bitwise(got, cache[steps], f"s2d {shape} r{radius} k{K} ly{ly}")
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+def test_s2d_default_config_vs_fp64(torch, st, oracle_mod, radius):
+    """Default (autoselected) configuration, 40 steps, against FP64."""
+    shape = (257, 1531)
+    c = synth.coefficients(600 + radius, 2, radius)
+    f = synth.grid_uniform(601, shape)
+    got, _ = gpu_run(torch, st, f, radius, c, 40)
+    assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, 40), "s2d default")
+    assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 40)) <= TOL_F64
+
+
+def test_config1_2d_r1_1024_10_steps(torch, st, oracle_mod):
+    """2D radius 1 on 1024x1024, U[0,1) values, seeded coefficients, 10 steps."""
+    c = synth.coefficients(101, 2, 1)
+    f = synth.grid_uniform(1, (1024, 1024))
+    got, _ = gpu_run(torch, st, f, 1, c, 10)
+    assert_bitwise(got, oracle_mod.star_run_f32(f, c, 1, 10), "1024^2 r1")
+    err = oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, 1, 10))
+    assert err <= TOL_F64, err
+
+
+def test_step_composition_and_zero_steps(torch, st):
+    c = synth.coefficients(7, 2, 3)
+    f = synth.grid_uniform(8, (200, 300))
+    plan = st.Plan(f.shape, 3, c)
+    x = torch.from_numpy(f).cuda()
+    a, b, z = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    plan.run(x, a, 11)
+    plan.run(x, b, 4)
+    plan.run(b.clone(), b, 7)
+    plan.run(x, z, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(z, x)
+
+
+def test_run_rejects_overlap_and_bad_steps(torch, st):
+    c = synth.coefficients(7, 2, 1)
+    plan = st.Plan((16, 16), 1, c)
+    x = torch.zeros(16, 16, device="cuda")
+    with pytest.raises(ValueError):
+        plan.run(x, x, 1)
+    with pytest.raises(ValueError):
+        plan.run(x, torch.empty_like(x), -1)
+    with pytest.raises(ValueError):
+        st.Plan((16, 16), 1, c, tune="k=9")
+    with pytest.raises(ValueError):
+        st.Plan((16, 16), 1, c, tune="bogus=1")
+
+
+@pytest.mark.parametrize("n", [1, 1000, 1 << 20, 3 * (1 << 20) + 17])
+def test_reduce_f64(torch, st, n):
+    x = torch.from_numpy(synth.uniform01_f32(5, n)).cuda()
+    ref = torch.from_numpy(synth.uniform01_f32(6, n).astype(np.float64) * 0.5).cuda()
+    md, mr, sm = st.reduce_f64(x, ref)
+    xn, rn = x.cpu().numpy().astype(np.float64), ref.cpu().numpy()
+    assert md == np.max(np.abs(xn - rn))
+    assert mr == np.max(np.abs(rn))
+    assert abs(sm - np.sum(xn)) <= 1e-12 * n
+    md2, mr2, sm2 = st.reduce_f64(x, None)
+    assert (md2, mr2) == (0.0, 0.0) and sm2 == sm
