@@ -6,6 +6,10 @@
 
 #include <type_traits>
 
+// Lambdas inside kernels are forced inline: the register queues they touch
+// must stay in registers, which needs every access at a compile-time index.
+#define STAR_INLINE __attribute__((always_inline))
+
 namespace star {
 
 // Points of a radius-4 3D star: 1 + 2*3*4.
@@ -48,6 +52,26 @@ __device__ __forceinline__ float from_upper_lane(float v) {
 // Value of v in lane `lane` (wave-uniform lane index), broadcast to all lanes.
 __device__ __forceinline__ float lane_value(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Raw buffer resources (gfx9 layout: stride 0, byte-range checked).  An
+// access at a byte offset >= the resource's size is dropped by the hardware
+// (a store writes nothing, a load returns 0), which masks lanes without a
+// branch.  Sizes must stay below 2^31 bytes so kOutOfRange is out of range.
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kOutOfRange = (int)0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, kRsrcWord3);
+}
+__device__ __forceinline__ void buffer_store4(__amdgpu_buffer_rsrc_t r, int off, float a, float b,
+                                              float c, float d) {
+    const v4i v = {__builtin_bit_cast(int, a), __builtin_bit_cast(int, b),
+                   __builtin_bit_cast(int, c), __builtin_bit_cast(int, d)};
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+__device__ __forceinline__ void buffer_store1(__amdgpu_buffer_rsrc_t r, int off, float a) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, a), r, off, 0, 0);
 }
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by block id.

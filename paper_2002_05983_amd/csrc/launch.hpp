@@ -22,6 +22,9 @@ struct Star2DArgs {
     Coefs cf;
 };
 constexpr int kMaxK2D = 8;
+// Largest K built per radius: K*R <= 16 keeps the unrolled queue code and
+// its registers in budget (K = 8, 8, 5, 4 for R = 1..4).
+constexpr int max_k2d(int R) { return 16 / R < kMaxK2D ? 16 / R : kMaxK2D; }
 constexpr int kVec2D = 4;
 // Output columns of one strip: a wavefront spans 64*4 columns, minus the
 // overlapped halo of roundup(K*R, 4) columns per side (Eq. (2) analogue).

@@ -16,20 +16,23 @@ namespace {
 // Resident wavefronts the 2D kernel aims for: 256 CUs x 4 SIMDs x 4.
 constexpr int64_t kTargetWaves2D = 4096;
 
+// Defaults measured on a 16384^2 grid (temporal degree and segment rows).
 int default_k2d(int R) {
     switch (R) {
         case 1: return 8;
-        case 2: return 4;
-        case 3: return 3;
-        default: return 2;
+        case 2: return 5;
+        case 3: return 4;
+        default: return 4;
     }
 }
 
 int default_ly(const stencil_plan_s *p, int K) {
     const int tx = star2d_tile_x(K, p->radius);
     const int64_t nstrips = (p->nx + tx - 1) / tx;
-    int64_t ly = (p->ny * nstrips + kTargetWaves2D - 1) / kTargetWaves2D;
-    ly = std::max<int64_t>(ly, 8 * K * p->radius);
+    int64_t ly = (p->radius == 4 && K == 4) ? 256 : 128;
+    // small grids: keep enough wavefronts to fill the chip
+    const int64_t want = (p->ny * nstrips + kTargetWaves2D - 1) / kTargetWaves2D;
+    ly = std::min<int64_t>(ly, std::max<int64_t>(want, 8 * K * p->radius));
     ly = std::min<int64_t>(ly, p->ny);
     return (int)std::max<int64_t>(ly, 1);
 }
@@ -86,8 +89,8 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
         }
     }
     if (p->variant == STAR_S2D) {
-        if (p->K < 1 || p->K > kMaxK2D)
-            return star_set_error(STENCIL_EINVAL, "2D k must be in 1..8");
+        if (p->K < 1 || p->K > max_k2d(R))
+            return star_set_error(STENCIL_EINVAL, "2D k must be in 1..16/R (at most 8)");
         if (p->ly == 0) p->ly = default_ly(p, p->K);
         if (p->ly < 1) return star_set_error(STENCIL_EINVAL, "ly must be >= 1");
         p->vec = kVec2D;

@@ -39,10 +39,10 @@ namespace {
 
 constexpr int VEC = kVec2D;
 
-// Cells of one row of one stage.  q holds the stage input's last P rows in
-// a circular buffer; CS is the slot of the centre row (compile-time).
-template <int R, int P, int CS>
-__device__ __forceinline__ void star2d_row(const float (&q)[P][VEC], const Coefs &cf,
+// Cells of one row of one stage.  q is a circular buffer of rows of the
+// stage's input (NS slots); CS is the slot of the centre row (compile-time).
+template <int R, int NS, int CS>
+__device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
                                            float (&res)[VEC]) {
     float left[R + 1], right[R + 1];
 #pragma unroll
@@ -57,8 +57,8 @@ __device__ __forceinline__ void star2d_row(const float (&q)[P][VEC], const Coefs
         for (int i = 1; i <= R; ++i) {
             const float w = (e - i >= 0) ? q[CS][e - i] : left[i - e];
             const float ea = (e + i < VEC) ? q[CS][e + i] : right[e + i - VEC + 1];
-            const float s = q[(CS - i + P) % P][e];
-            const float n = q[(CS + i) % P][e];
+            const float s = q[(CS - i + NS) % NS][e];
+            const float n = q[(CS + i) % NS][e];
             acc = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], w, acc);
             acc = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], ea, acc);
             acc = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], s, acc);
@@ -68,17 +68,22 @@ __device__ __forceinline__ void star2d_row(const float (&q)[P][VEC], const Coefs
     }
 }
 
-template <int R, int K, bool ALIGNED>
+template <int R, int K, int M, bool ALIGNED>
 __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ src,
                                                      float *__restrict__ dst, int nx, int ny,
                                                      int ly, int nstrips, int nwaves, Coefs cf) {
-    constexpr int P = 2 * R + 1;
+    constexpr int P = 2 * R + 1;  // rows a stage keeps: its y-window
+    constexpr int NQ = M * P;     // input ring: y-window plus (M-1)*P rows in flight
     constexpr int H = star2d_halo(K, R);
     constexpr int TX = star2d_tile_x(K, R);
     static_assert(R <= VEC, "x-neighbours must come from the adjacent lane");
 
     const int lane = threadIdx.x & 63;
-    const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    // Everything below that does not depend on `lane` is wave-uniform; the
+    // readfirstlane makes the compiler keep it in scalar registers and turn
+    // the per-row conditions into scalar branches.
+    const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 +
+                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
     const int strip = wave % nstrips;
     const int seg = wave / nstrips;
@@ -88,6 +93,7 @@ __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ s
     const int y1 = min(y0 + ly, ny);
     const int jstart = y0 - K * R;
     const int niter = (y1 - y0) + 2 * K * R;
+    const int jlast = jstart + niter - 1;
     const bool left_edge = xs < 0;
     const bool right_edge = xs + 64 * VEC > nx;
     const int out_lo = max(xs + H, 0);
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ s
 
     // Clamp in x: cells left of column 0 take column 0, cells right of
     // column nx-1 take column nx-1 (of the same row and stage).
-    auto xfix = [&](float (&v)[VEC]) {
+    auto xfix = [&](float (&v)[VEC]) STAR_INLINE {
         if (left_edge) {
             const int l0 = (-xs) / VEC;  // lane whose element 0 is column 0
             const float b = lane_value(v[0], l0);
@@ -116,85 +122,108 @@ __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ s
         }
     };
 
-    auto load_row = [&](int j, float (&v)[VEC]) {
-        const float *row = src + (size_t)clampi(j, ny) * (size_t)nx;
+    // Issues the load of input row j (clamped to the grid in y) into v.
+    // Rows past the segment's last one are never needed; they are re-read
+    // as the last row.  The x-clamp of a loaded row is applied when the row
+    // enters stage 1 (consume_row), so no load is waited for early.
+    auto load_row = [&](int j, float (&v)[VEC]) STAR_INLINE {
+        const float *row = src + (size_t)clampi(min(j, jlast), ny) * (size_t)nx;
         if constexpr (ALIGNED) {
             const int c = min(max(col0, 0), nx - VEC);
             const float4 t = *reinterpret_cast<const float4 *>(row + c);
             v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-            xfix(v);
         } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[e] = row[clampi(col0 + e, nx)];
         }
     };
 
-    float pf[P][VEC];     // rows loaded ahead (prefetch distance P)
-    float q[K][P][VEC];   // q[s]: last P rows of the stage-s field (s = 0: input)
+    // q0: ring of NQ input rows, loaded straight into their slots.
+    // q[s-1] (s = 2..K): last P rows of the stage-(s-1) field.
+    float q0[NQ][VEC];
+    float q[K > 1 ? K - 1 : 1][P][VEC];
 #pragma unroll
-    for (int s = 0; s < K; ++s)
+    for (int s = 0; s < (K > 1 ? K - 1 : 1); ++s)
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int e = 0; e < VEC; ++e) q[s][p][e] = 0.0f;
+#pragma unroll
+    for (int p = 0; p < NQ; ++p)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) q0[p][e] = 0.0f;
 
-    static_for<0, P>([&](auto phc) {
+    constexpr int DIST = NQ - P;  // prefetch distance in rows
+    static_for<0, DIST>([&](auto phc) STAR_INLINE {
         constexpr int PH = decltype(phc)::value;
-        if (PH < niter) load_row(jstart + PH, pf[PH]);
+        load_row(jstart + PH, q0[PH]);
     });
 
-    for (int n0 = 0; n0 < niter; n0 += P) {
-        static_for<0, P>([&](auto phc) {
-            constexpr int PH = decltype(phc)::value;
-            const int n = n0 + PH;
-            if (n < niter) {
-                const int j = jstart + n;  // row entering stage 1
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) q[0][PH][e] = pf[PH][e];
-                if (n + P < niter) load_row(j + P, pf[PH]);
+    // One streamed row: iteration n, ring slot PH = n mod NQ.
+    auto step_row = [&](auto phc, int n) STAR_INLINE {
+        constexpr int PH = decltype(phc)::value;
+        const int j = jstart + n;  // row entering stage 1
+        load_row(j + DIST, q0[(PH + DIST) % NQ]);
+        if constexpr (ALIGNED) xfix(q0[PH]);
 
-                static_for<1, K + 1>([&](auto sc) {
-                    constexpr int S = decltype(sc)::value;
-                    constexpr int CS = (PH - R + P) % P;
-                    const int r = j - S * R;  // row produced by stage S
-                    float res[VEC];
-                    star2d_row<R, P, CS>(q[S - 1], cf, res);
-                    if constexpr (S < K) {
-                        if (r >= ny) {
+        static_for<1, K + 1>([&](auto sc) STAR_INLINE {
+            constexpr int S = decltype(sc)::value;
+            const int r = j - S * R;  // row produced by stage S
+            float res[VEC];
+            if constexpr (S == 1)
+                star2d_row<R, NQ, (PH - R + NQ) % NQ>(q0, cf, res);
+            else
+                star2d_row<R, P, (PH % P - R + P) % P>(q[S - 2], cf, res);
+            if constexpr (S < K) {
+                constexpr int W = PH % P;  // slot of this row in the stage's window
+                if (r >= ny) {
 #pragma unroll
-                            for (int e = 0; e < VEC; ++e) res[e] = q[S][(PH + P - 1) % P][e];
-                        } else {
-                            xfix(res);
-                        }
+                    for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(W + P - 1) % P][e];
+                } else {
+                    xfix(res);
+                }
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) q[S][PH][e] = res[e];
-                        if (r == 0) {
-                            static_for<1, R + 1>([&](auto mc) {
-                                constexpr int M = decltype(mc)::value;
+                for (int e = 0; e < VEC; ++e) q[S - 1][W][e] = res[e];
+                if (r == 0) {
+                    static_for<1, R + 1>([&](auto mc) STAR_INLINE {
+                        constexpr int MM = decltype(mc)::value;
 #pragma unroll
-                                for (int e = 0; e < VEC; ++e) q[S][(PH - M + P) % P][e] = res[e];
-                            });
-                        }
-                    } else {
-                        if (r >= y0 && r < y1) {
-                            float *row = dst + (size_t)r * (size_t)nx;
-                            if (ALIGNED && col0 >= out_lo && col0 + VEC <= out_hi) {
-                                *reinterpret_cast<float4 *>(row + col0) =
-                                    make_float4(res[0], res[1], res[2], res[3]);
-                            } else if (!ALIGNED) {
+                        for (int e = 0; e < VEC; ++e) q[S - 1][(W - MM + P) % P][e] = res[e];
+                    });
+                }
+            } else {
+                // Stage K: write row r.  The store is issued on every row;
+                // rows of the wind-up and lanes outside the output tile get
+                // an out-of-range offset and write nothing.
+                const bool row_ok = r >= y0 && r < y1;
+                const auto rs = buffer_rsrc(dst + (size_t)clampi(r, ny) * (size_t)nx, nx * 4);
+                if constexpr (ALIGNED) {
+                    const bool ok = row_ok && col0 >= out_lo && col0 + VEC <= out_hi;
+                    buffer_store4(rs, ok ? col0 * 4 : kOutOfRange, res[0], res[1], res[2], res[3]);
+                } else {
 #pragma unroll
-                                for (int e = 0; e < VEC; ++e) {
-                                    const int c = col0 + e;
-                                    if (c >= out_lo && c < out_hi) row[c] = res[e];
-                                }
-                            }
-                        }
+                    for (int e = 0; e < VEC; ++e) {
+                        const int c = col0 + e;
+                        const bool ok = row_ok && c >= out_lo && c < out_hi;
+                        buffer_store1(rs, ok ? c * 4 : kOutOfRange, res[e]);
                     }
-                });
+                }
             }
         });
+    };
+
+    int n0 = 0;
+    for (; n0 + NQ <= niter; n0 += NQ) {
+        static_for<0, NQ>([&](auto phc) STAR_INLINE { step_row(phc, n0 + decltype(phc)::value); });
     }
+    static_for<0, NQ>([&](auto phc) STAR_INLINE {
+        if (n0 + decltype(phc)::value < niter) step_row(phc, n0 + decltype(phc)::value);
+    });
 }
+
+// Input-ring multiple: deeper prefetch for the memory-bound small-K passes.
+template <int K>
+constexpr int ring_mult() { return K * STAR_R <= 2 ? 3 : 2; }
 
 template <int K, bool AL>
 hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
@@ -204,14 +233,18 @@ hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
     const int64_t nwaves = (int64_t)nstrips * nsegs;
     if (nwaves > (int64_t)1 << 30) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    hipLaunchKernelGGL((star2d_stream<STAR_R, K, AL>), dim3(blocks), dim3(256), 0, stream, a.src,
+    hipLaunchKernelGGL((star2d_stream<STAR_R, K, ring_mult<K>(), AL>), dim3(blocks), dim3(256), 0, stream, a.src,
                        a.dst, a.nx, a.ny, a.ly, nstrips, (int)nwaves, a.cf);
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t launch_al(const Star2DArgs &a, hipStream_t stream) {
-    return a.aligned ? launch_k<K, true>(a, stream) : launch_k<K, false>(a, stream);
+    if constexpr (K > max_k2d(STAR_R)) {
+        return hipErrorInvalidValue;
+    } else {
+        return a.aligned ? launch_k<K, true>(a, stream) : launch_k<K, false>(a, stream);
+    }
 }
 
 }  // namespace
