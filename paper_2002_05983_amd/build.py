@@ -26,6 +26,7 @@ ARCH = "gfx950"
 # Host-only translation units and (source, defines) device units.
 HOST_UNITS = ["api.cpp", "plan.cpp"]
 DEVICE_UNITS = [("naive.hip", {}), ("reduce.hip", {})] + [("star2d.hip", {"STAR_R": r}) for r in (1, 2, 3, 4)]
+DEVICE_UNITS += [("star3d.hip", {"STAR_R": r}) for r in (1, 2, 3, 4)]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-fvisibility=hidden", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function"]

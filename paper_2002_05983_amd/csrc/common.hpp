@@ -29,6 +29,8 @@ __host__ __device__ constexpr int coef_index(int d, int i) {
 }
 enum : int { kW = 0, kE = 1, kS = 2, kN = 3, kB = 4, kA = 5 };
 
+constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
+
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
     if constexpr (I < N) {
@@ -40,14 +42,18 @@ __device__ __forceinline__ void static_for(F &&f) {
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
 
 // Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1, full-rate VALU
-// moves).  The lane with no source gets 0.
-__device__ __forceinline__ float from_lower_lane(float v) {
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+// moves).  The lane with no source (lane 0, resp. lane 63) gets `edge`:
+// callers pass the lane's own outermost cell, which is the clamped value
+// when a row starts (ends) at that lane.
+__device__ __forceinline__ float from_lower_lane(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x138,
+                                                                 0xf, 0xf, false));
 }
-__device__ __forceinline__ float from_upper_lane(float v) {
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+__device__ __forceinline__ float from_upper_lane(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x130,
+                                                                 0xf, 0xf, false));
 }
 // Value of v in lane `lane` (wave-uniform lane index), broadcast to all lanes.
 __device__ __forceinline__ float lane_value(float v, int lane) {

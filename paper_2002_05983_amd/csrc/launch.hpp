@@ -36,4 +36,27 @@ hipError_t launch_star2d_r2(const Star2DArgs &a, hipStream_t stream);
 hipError_t launch_star2d_r3(const Star2DArgs &a, hipStream_t stream);
 hipError_t launch_star2d_r4(const Star2DArgs &a, hipStream_t stream);
 
+// 3D xy-tile / z-stream kernel fusing K steps per pass.
+struct Star3DArgs {
+    const float *src;
+    float *dst;
+    int nx, ny, nz;
+    int K;        // steps fused in this pass
+    int vec;      // cells per lane along x: 4 or 8 (row of 256 or 512 columns)
+    int nw;       // wavefronts per workgroup = tile rows incl. 2*K*R halo rows
+    int lz;       // output planes per z-segment
+    bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
+    Coefs cf;
+};
+// Largest K built per radius: the tile keeps >= 8 output rows of 16 for
+// R = 1 and every build stays within 128 VGPRs without spilling.
+constexpr int max_k3d(int R) { return R == 1 ? 4 : R == 2 ? 2 : 1; }
+// Widest row: 512 columns (vec 8) for aligned single-step passes of R <= 2.
+constexpr bool vec8_ok(int R, int K, bool aligned) { return K == 1 && R <= 2 && aligned; }
+
+hipError_t launch_star3d_r1(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r2(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r3(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r4(const Star3DArgs &a, hipStream_t stream);
+
 }  // namespace star

@@ -37,6 +37,22 @@ int default_ly(const stencil_plan_s *p, int K) {
     return (int)std::max<int64_t>(ly, 1);
 }
 
+// z-segment length: enough workgroups for 2 per CU, without letting the
+// 2*K*R wind-up planes exceed a quarter of a segment.
+int default_lz(const stencil_plan_s *p) {
+    const int W = 64 * p->vec;
+    const int R = p->radius, K = p->K;
+    const int hx = (int)p->nx > W ? (K * R + p->vec - 1) / p->vec * p->vec : 0;
+    const int64_t tx = (int)p->nx > W ? W - 2 * hx : p->nx;
+    const int64_t ty = p->s3_rows - 2 * K * R;
+    const int64_t tiles = ((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty);
+    int64_t nseg = (512 + tiles - 1) / tiles;
+    int64_t lz = (p->nz + nseg - 1) / nseg;
+    lz = std::max<int64_t>(lz, 8 * K * R);
+    lz = std::min<int64_t>(lz, p->nz);
+    return (int)std::max<int64_t>(lz, 1);
+}
+
 bool parse_int(const char *s, int *out) {
     char *end = nullptr;
     long v = strtol(s, &end, 10);
@@ -54,8 +70,11 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
         p->K = default_k2d(R);
         p->ly = 0;
     } else {
-        p->variant = STAR_NAIVE;
+        p->variant = STAR_S3D;
         p->K = 1;
+        p->vec = 0;   // chosen below from the grid width
+        p->s3_rows = 16;
+        p->s3_lz = 0;
     }
     if (tune && *tune) {
         p->tuned_by = "override";
@@ -83,6 +102,12 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
                 p->K = v;
             } else if (key == "ly" && p->ndim == 2) {
                 p->ly = v;
+            } else if (key == "lz" && p->ndim == 3) {
+                p->s3_lz = v;
+            } else if (key == "nw" && p->ndim == 3) {
+                p->s3_rows = v;
+            } else if (key == "vec" && p->ndim == 3) {
+                p->vec = v;
             } else {
                 return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
             }
@@ -97,6 +122,22 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
         p->tile[0] = star2d_tile_x(p->K, R);
         p->tile[1] = p->ly;
         p->tile[2] = 1;
+    } else if (p->variant == STAR_S3D) {
+        if (p->K < 1 || p->K > max_k3d(R))
+            return star_set_error(STENCIL_EINVAL, "3D k must be in 1..4/2/1/1 for R = 1..4");
+        if (p->s3_rows < 2 * p->K * R + 1 || p->s3_rows > 16)
+            return star_set_error(STENCIL_EINVAL, "3D nw must be > 2*k*R and <= 16");
+        const bool al = p->nx % 4 == 0;
+        if (p->vec == 0) p->vec = (p->nx > 256 && p->nx <= 512 && vec8_ok(R, p->K, al)) ? 8 : 4;
+        if (p->vec != 4 && !(p->vec == 8 && vec8_ok(R, p->K, al)))
+            return star_set_error(STENCIL_EINVAL, "3D vec must be 4, or 8 for aligned k=1, R<=2");
+        if (p->s3_lz == 0) p->s3_lz = default_lz(p);
+        if (p->s3_lz < 1) return star_set_error(STENCIL_EINVAL, "lz must be >= 1");
+        const int W = 64 * p->vec;
+        const int hx = (int)p->nx > W ? (p->K * R + p->vec - 1) / p->vec * p->vec : 0;
+        p->tile[0] = (int)p->nx > W ? W - 2 * hx : (int)p->nx;
+        p->tile[1] = p->s3_rows - 2 * p->K * R;
+        p->tile[2] = p->s3_lz;
     } else if (p->variant == STAR_NAIVE) {
         if (p->K != 1) return star_set_error(STENCIL_EINVAL, "naive variant has k = 1");
         p->vec = 1;
@@ -137,6 +178,28 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
             }
             return hipErrorInvalidValue;
         }
+        case STAR_S3D: {
+            Star3DArgs a;
+            a.src = src;
+            a.dst = dst;
+            a.nx = (int)p->nx;
+            a.ny = (int)p->ny;
+            a.nz = (int)p->nz;
+            a.K = k;
+            a.vec = (k == p->K) ? p->vec : 4;  // a tail pass may not fit the wide row
+            a.nw = p->s3_rows;
+            a.lz = p->s3_lz;
+            a.aligned = (p->nx % 4 == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
+            if (a.vec == 8 && !a.aligned) a.vec = 4;
+            a.cf = p->cf;
+            switch (p->radius) {
+                case 1: return launch_star3d_r1(a, stream);
+                case 2: return launch_star3d_r2(a, stream);
+                case 3: return launch_star3d_r3(a, stream);
+                case 4: return launch_star3d_r4(a, stream);
+            }
+            return hipErrorInvalidValue;
+        }
         default:
             return hipErrorInvalidValue;
     }
@@ -145,9 +208,14 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
 std::string plan_describe(const stencil_plan_s *p) {
     char buf[256];
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
-    snprintf(buf, sizeof buf, "variant=%s ndim=%d R=%d K=%d tile=%dx%dx%d vec=%d ly=%d by=%s", v,
-             p->ndim, p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->ly,
-             p->tuned_by.c_str());
+    if (p->variant == STAR_S3D)
+        snprintf(buf, sizeof buf, "variant=s3d ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d nw=%d lz=%d by=%s",
+                 p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_rows,
+                 p->s3_lz, p->tuned_by.c_str());
+    else
+        snprintf(buf, sizeof buf, "variant=%s ndim=%d R=%d K=%d tile=%dx%dx%d vec=%d ly=%d by=%s", v,
+                 p->ndim, p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->ly,
+                 p->tuned_by.c_str());
     return buf;
 }
 

@@ -47,8 +47,8 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
     float left[R + 1], right[R + 1];
 #pragma unroll
     for (int k = 1; k <= R; ++k) {
-        left[k] = from_lower_lane(q[CS][VEC - k]);  // column base - k
-        right[k] = from_upper_lane(q[CS][k - 1]);   // column base + VEC - 1 + k
+        left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);  // column base - k
+        right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);   // column base + VEC - 1 + k
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {

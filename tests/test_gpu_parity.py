@@ -100,6 +100,43 @@ def test_s2d_default_config_vs_fp64(torch, st, oracle_mod, radius):
     assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 40)) <= TOL_F64
 
 
+# (nz, ny, nx) shapes: one 256- or 512-column strip, several strips, ragged x
+# (unaligned), small sides, several y-tiles and z-segments.
+S3D_SHAPES = [(1, 1, 1), (3, 2, 5), (4, 5, 6), (9, 17, 33), (20, 37, 300), (13, 40, 513),
+              (7, 33, 600), (30, 50, 64), (6, 3, 257)]
+MAX_K3D = {1: 4, 2: 2, 3: 1, 4: 1}
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", S3D_SHAPES)
+def test_s3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    c = synth.coefficients(700 + radius, 3, radius)
+    f = synth.grid_uniform(800 + radius, shape)
+    cache = {}
+    for K in range(1, MAX_K3D[radius] + 1):
+        for nw, lz in ((16, 5), (2 * K * radius + 2, 32)):
+            steps = 2 * K + 1
+            if steps not in cache:
+                cache[steps] = oracle_mod.star_run_f32(f, c, radius, steps)
+            got, desc = gpu_run(torch, st, f, radius, c, steps, tune=f"k={K},nw={nw},lz={lz}")
+            assert "variant=s3d" in desc, desc
+            assert_bitwise(got, cache[steps], f"s3d {shape} r{radius} k{K} nw{nw} lz{lz} [{desc}]")
+        if K == 1 and shape[2] % 4 == 0 and 256 < shape[2] <= 512 and radius <= 2:
+            got, desc = gpu_run(torch, st, f, radius, c, 3, tune="k=1,vec=8,lz=7")
+            assert "vec=8" in desc
+            assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, 3), f"s3d vec8 {shape} r{radius}")
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+def test_s3d_default_config_vs_fp64(torch, st, oracle_mod, radius):
+    shape = (40, 45, 130)
+    c = synth.coefficients(900 + radius, 3, radius)
+    f = synth.grid_uniform(901, shape)
+    got, _ = gpu_run(torch, st, f, radius, c, 12)
+    assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, 12), "s3d default")
+    assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 12)) <= TOL_F64
+
+
 def test_config1_2d_r1_1024_10_steps(torch, st, oracle_mod):
     """2D radius 1 on 1024x1024, U[0,1) values, seeded coefficients, 10 steps."""
     c = synth.coefficients(101, 2, 1)
