@@ -6,7 +6,12 @@ on a 16384 x 16384 FP32 grid of U[0,1) values, 1000 time steps per radius,
 each radius with its plan's temporal degree K.  Inputs are resident in HBM
 before timing starts.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-tune] [--no-3d]
+
+Each plan is autotuned (every feasible kernel configuration timed at the
+real shape) before the timed region.  A secondary leg measures the 3D
+workload (512^3, radius 1..4, 200 steps each) the same way and reports it
+under "extra".
 
 value: whole-job cell updates per second (GCell/s, Eq. (3) of the paper read
 as cells*iterations/time), summed over the four radii.
@@ -61,12 +66,46 @@ def cpu_baseline(f0, coeffs_by_r, sample_steps: int = 2):
                       f"({updates:.3e} cell updates in {t:.1f} s)"}
 
 
+def bench_3d(stencil, synth, torch, dev, side=512, time_steps=200, reps=2, tune=True):
+    """3D star stencils r=1..4 on side^3 FP32 (U[0,1)), time_steps steps each."""
+    shape = (side, side, side)
+    x = torch.from_numpy(synth.grid_uniform(2, shape)).to(dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    rows, tot_ms = [], 0.0
+    for r in RADII:
+        p = stencil.Plan(shape, r, synth.coefficients(2000 + r, 3, r))
+        if tune:
+            p.autotune(x, y, stream=stream)
+        p.run(x, y, time_steps, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(stream)
+        for _ in range(reps):
+            p.run(x, y, time_steps, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b) / reps
+        tot_ms += ms
+        gc = x.numel() * time_steps / (ms / 1e3) / 1e9
+        rows.append({"radius": r, "ms": round(ms, 3), "GCell/s": round(gc, 1),
+                     "GFLOP/s": round(gc * flop_per_cell(3, r), 1),
+                     "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
+                     "config": p.describe()})
+        p.close()
+    total = x.numel() * time_steps * len(RADII) / (tot_ms / 1e3) / 1e9
+    return {"workload": f"3D star stencils r=1..4, {side}^3 FP32 U[0,1), {time_steps} steps per "
+                        f"radius, clamp", "GCell/s": round(total, 1), "per_radius": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="use the plans' default configurations")
+    ap.add_argument("--no-3d", action="store_true", help="skip the secondary 3D leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -89,6 +128,9 @@ def main():
     y = torch.empty_like(x)
     plans = {r: stencil.Plan(shape, r, coeffs[r]) for r in RADII}
     stream = torch.cuda.current_stream(dev)
+    if not args.no_tune:
+        for r in RADII:
+            plans[r].autotune(x, y, stream=stream)
 
     def one_step(record=None):
         for r in RADII:
@@ -174,6 +216,9 @@ def main():
     for p in plans.values():
         p.close()
     del x, y
+    torch.cuda.empty_cache()
+    if not args.no_3d:
+        out["extra"] = {"3d": bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f0, coeffs)
     print(json.dumps(out), flush=True)

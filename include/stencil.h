@@ -121,6 +121,22 @@ STENCIL_API int stencil_run_batched(int n, const stencil_plan_t *plans, const fl
                         float *const *outs, const int64_t *steps, void *stream);
 
 /*
+ * Measured autotuning (the empirical counterpart of the paper's model-guided
+ * parameter search, Sec. V.A): times every feasible configuration of the
+ * plan -- temporal degree K, segment length, lanes and cells per row -- on
+ * the caller's grids at the plan's real shape, with HIP events on `stream`,
+ * keeps the fastest in the plan and, when the environment variable
+ * STENCIL_TUNE_CACHE names a writable file, records it there; later plans
+ * of the same problem (ndim, radius, storage, dims) read it back.
+ *   in, out  device grids as for stencil_run (`out` is overwritten).
+ *   report   optional host buffer (NULL allowed) for a text table of the
+ *            candidates: "<config> <GCell/s>" per line, best first.
+ * Synchronises `stream`.  Errors: EINVAL, EDEVICE.
+ */
+STENCIL_API int stencil_plan_autotune(stencil_plan_t plan, const float *in, float *out,
+                                      char *report, size_t report_len, void *stream);
+
+/*
  * Reports the plan's configuration.  Any output pointer may be NULL.
  *   K          time steps fused per pass.
  *   tile       output tile extent in x, y, z (cells; z = 1 in 2D).

@@ -183,21 +183,8 @@ int stencil_run(stencil_plan_t plan, const float *in, float *out, int64_t steps,
     if (ranges_overlap(in, out, bytes)) return fail(STENCIL_EINVAL, "in and out overlap");
     if (ranges_overlap(in, plan->scratch, bytes) || ranges_overlap(out, plan->scratch, bytes))
         return fail(STENCIL_EINVAL, "in/out overlap the plan's scratch");
-    hipStream_t st = (hipStream_t)stream;
-    if (steps == 0) {
-        hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, st);
-        return e == hipSuccess ? STENCIL_OK : hip_fail(e, "hipMemcpyAsync");
-    }
-    std::vector<int> passes;
-    plan_pass_schedule(plan, steps, passes);
-    const int np = (int)passes.size();
-    const float *src = in;
-    for (int p = 0; p < np; ++p) {
-        float *dst = ((np - 1 - p) % 2 == 0) ? out : plan->scratch;
-        hipError_t e = plan_launch_pass(plan, passes[p], src, dst, st);
-        if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        src = dst;
-    }
+    const hipError_t e = plan_enqueue(plan, in, out, steps, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, steps == 0 ? "hipMemcpyAsync" : "kernel launch");
     return STENCIL_OK;
 }
 

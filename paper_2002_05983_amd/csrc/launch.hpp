@@ -42,8 +42,9 @@ struct Star3DArgs {
     float *dst;
     int nx, ny, nz;
     int K;        // steps fused in this pass
-    int vec;      // cells per lane along x: 4 or 8 (row of 256 or 512 columns)
-    int nw;       // wavefronts per workgroup = tile rows incl. 2*K*R halo rows
+    int vec;      // cells per lane along x: 4 or 8
+    int wl;       // lanes per tile row: 64 or 32 (two rows per wavefront)
+    int nw;       // wavefronts per workgroup; tile rows = nw*64/wl incl. 2*K*R halo rows
     int lz;       // output planes per z-segment
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
     Coefs cf;

@@ -40,11 +40,12 @@ int default_ly(const stencil_plan_s *p, int K) {
 // z-segment length: enough workgroups for 2 per CU, without letting the
 // 2*K*R wind-up planes exceed a quarter of a segment.
 int default_lz(const stencil_plan_s *p) {
-    const int W = 64 * p->vec;
+    const int W = p->s3_lanes * p->vec;
     const int R = p->radius, K = p->K;
-    const int hx = (int)p->nx > W ? (K * R + p->vec - 1) / p->vec * p->vec : 0;
-    const int64_t tx = (int)p->nx > W ? W - 2 * hx : p->nx;
-    const int64_t ty = p->s3_rows - 2 * K * R;
+    const bool halo = (int)p->nx > W || p->s3_lanes != 64;
+    const int hx = halo ? (K * R + p->vec - 1) / p->vec * p->vec : 0;
+    const int64_t tx = halo ? W - 2 * hx : p->nx;
+    const int64_t ty = p->s3_rows * (64 / p->s3_lanes) - 2 * K * R;
     const int64_t tiles = ((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty);
     int64_t nseg = (512 + tiles - 1) / tiles;
     int64_t lz = (p->nz + nseg - 1) / nseg;
@@ -63,21 +64,41 @@ bool parse_int(const char *s, int *out) {
 
 }  // namespace
 
+static int plan_apply(stencil_plan_s *p, const char *tune);
+
 int plan_configure(stencil_plan_s *p, const char *tune) {
+    if (tune && *tune) {
+        const int rc = plan_apply(p, tune);
+        p->tuned_by = "override";
+        return rc;
+    }
+    std::string cached;
+    if (tune_cache_lookup(p, cached) && plan_apply(p, cached.c_str()) == STENCIL_OK) {
+        p->tuned_by = "cache";
+        return STENCIL_OK;
+    }
+    const int rc = plan_apply(p, nullptr);
+    p->tuned_by = "default";
+    return rc;
+}
+
+static int plan_apply(stencil_plan_s *p, const char *tune) {
     const int R = p->radius;
     if (p->ndim == 2) {
         p->variant = STAR_S2D;
         p->K = default_k2d(R);
         p->ly = 0;
     } else {
+        // defaults measured on a 512^3 grid
         p->variant = STAR_S3D;
-        p->K = 1;
+        p->K = R == 1 ? 4 : R == 2 ? 2 : 1;
         p->vec = 0;   // chosen below from the grid width
         p->s3_rows = 16;
+        p->s3_lanes = 32;
         p->s3_lz = 0;
     }
+    p->ly = (p->ndim == 2) ? 0 : p->ly;
     if (tune && *tune) {
-        p->tuned_by = "override";
         std::string s(tune);
         size_t pos = 0;
         while (pos <= s.size()) {
@@ -108,6 +129,8 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
                 p->s3_rows = v;
             } else if (key == "vec" && p->ndim == 3) {
                 p->vec = v;
+            } else if (key == "wl" && p->ndim == 3) {
+                p->s3_lanes = v;
             } else {
                 return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
             }
@@ -125,18 +148,23 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
     } else if (p->variant == STAR_S3D) {
         if (p->K < 1 || p->K > max_k3d(R))
             return star_set_error(STENCIL_EINVAL, "3D k must be in 1..4/2/1/1 for R = 1..4");
-        if (p->s3_rows < 2 * p->K * R + 1 || p->s3_rows > 16)
-            return star_set_error(STENCIL_EINVAL, "3D nw must be > 2*k*R and <= 16");
+        if (p->s3_lanes != 64 && p->s3_lanes != 32)
+            return star_set_error(STENCIL_EINVAL, "3D wl must be 64 or 32");
+        const int rows = p->s3_rows * (64 / p->s3_lanes);
+        if (rows < 2 * p->K * R + 1 || p->s3_rows > 16 || p->s3_rows < 1)
+            return star_set_error(STENCIL_EINVAL, "3D nw must be <= 16 with nw*64/wl > 2*k*R");
         const bool al = p->nx % 4 == 0;
-        if (p->vec == 0) p->vec = (p->nx > 256 && p->nx <= 512 && vec8_ok(R, p->K, al)) ? 8 : 4;
-        if (p->vec != 4 && !(p->vec == 8 && vec8_ok(R, p->K, al)))
-            return star_set_error(STENCIL_EINVAL, "3D vec must be 4, or 8 for aligned k=1, R<=2");
+        if (p->vec == 0)
+            p->vec = (p->s3_lanes == 64 && p->nx > 256 && p->nx <= 512 && vec8_ok(R, p->K, al)) ? 8 : 4;
+        if (p->vec != 4 && !(p->vec == 8 && p->s3_lanes == 64 && vec8_ok(R, p->K, al)))
+            return star_set_error(STENCIL_EINVAL, "3D vec must be 4, or 8 for wl=64, aligned k=1, R<=2");
         if (p->s3_lz == 0) p->s3_lz = default_lz(p);
         if (p->s3_lz < 1) return star_set_error(STENCIL_EINVAL, "lz must be >= 1");
-        const int W = 64 * p->vec;
-        const int hx = (int)p->nx > W ? (p->K * R + p->vec - 1) / p->vec * p->vec : 0;
-        p->tile[0] = (int)p->nx > W ? W - 2 * hx : (int)p->nx;
-        p->tile[1] = p->s3_rows - 2 * p->K * R;
+        const int W = p->s3_lanes * p->vec;
+        const bool halo = (int)p->nx > W || p->s3_lanes != 64;
+        const int hx = halo ? (p->K * R + p->vec - 1) / p->vec * p->vec : 0;
+        p->tile[0] = halo ? W - 2 * hx : (int)p->nx;
+        p->tile[1] = rows - 2 * p->K * R;
         p->tile[2] = p->s3_lz;
     } else if (p->variant == STAR_NAIVE) {
         if (p->K != 1) return star_set_error(STENCIL_EINVAL, "naive variant has k = 1");
@@ -144,6 +172,24 @@ int plan_configure(stencil_plan_s *p, const char *tune) {
         p->tile[0] = p->tile[1] = p->tile[2] = 1;
     }
     return STENCIL_OK;
+}
+
+hipError_t plan_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
+                        hipStream_t stream) {
+    if (steps == 0)
+        return hipMemcpyAsync(out, in, (size_t)p->ncells * sizeof(float), hipMemcpyDeviceToDevice,
+                              stream);
+    std::vector<int> passes;
+    plan_pass_schedule(p, steps, passes);
+    const int np = (int)passes.size();
+    const float *src = in;
+    for (int i = 0; i < np; ++i) {
+        float *dst = ((np - 1 - i) % 2 == 0) ? out : p->scratch;
+        const hipError_t e = plan_launch_pass(p, passes[i], src, dst, stream);
+        if (e != hipSuccess) return e;
+        src = dst;
+    }
+    return hipSuccess;
 }
 
 void plan_pass_schedule(const stencil_plan_s *p, int64_t steps, std::vector<int> &passes) {
@@ -188,6 +234,7 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
             a.K = k;
             a.vec = (k == p->K) ? p->vec : 4;  // a tail pass may not fit the wide row
             a.nw = p->s3_rows;
+            a.wl = p->s3_lanes;
             a.lz = p->s3_lz;
             a.aligned = (p->nx % 4 == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
             if (a.vec == 8 && !a.aligned) a.vec = 4;
@@ -209,9 +256,10 @@ std::string plan_describe(const stencil_plan_s *p) {
     char buf[256];
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
     if (p->variant == STAR_S3D)
-        snprintf(buf, sizeof buf, "variant=s3d ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d nw=%d lz=%d by=%s",
-                 p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_rows,
-                 p->s3_lz, p->tuned_by.c_str());
+        snprintf(buf, sizeof buf,
+                 "variant=s3d ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d by=%s",
+                 p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_lanes,
+                 p->s3_rows, p->s3_lz, p->tuned_by.c_str());
     else
         snprintf(buf, sizeof buf, "variant=%s ndim=%d R=%d K=%d tile=%dx%dx%d vec=%d ly=%d by=%s", v,
                  p->ndim, p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->ly,

@@ -42,6 +42,12 @@ struct stencil_plan_s {
 
 // Chooses the kernel configuration; `tune` may override it (NULL = auto).
 int plan_configure(stencil_plan_s *p, const char *tune);
+// Enqueues `steps` time steps from in to out (passes ping-pong between out
+// and the plan's scratch; the last pass writes out).
+hipError_t plan_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
+                        hipStream_t stream);
+// Configuration recorded for this problem in the tuning cache, if any.
+bool tune_cache_lookup(const stencil_plan_s *p, std::string &config);
 // Splits `steps` into the K of each pass.
 void plan_pass_schedule(const stencil_plan_s *p, int64_t steps, std::vector<int> &passes);
 // Enqueues one pass of `k` fused steps from src to dst.

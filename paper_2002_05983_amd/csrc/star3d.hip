@@ -5,11 +5,13 @@
 // Method (Sec. III.A of the paper: 2.5D spatial blocking -- block x and y,
 // stream z -- combined with temporal blocking by a chain of K stages and
 // overlapped halos, Eq. (2)):
-//   * A workgroup owns an xy tile: NW wavefronts, one per tile row.  A
-//     wavefront's 64 lanes hold VEC consecutive cells each, so a row spans
-//     64*VEC columns; when the grid is at most that wide the whole x extent
-//     is one tile and needs no x halo, otherwise tiles overlap by
-//     Hx = roundup(K*R, VEC) columns per side.
+//   * A workgroup owns an xy tile: NW wavefronts of 64/WL tile rows each.
+//     WL lanes of a wavefront hold VEC consecutive cells each, so a row spans
+//     WL*VEC columns.  With WL = 64, a grid at most that wide is one tile and
+//     needs no x halo; otherwise tiles overlap by Hx = roundup(K*R, VEC)
+//     columns per side (the lanes at the ends of a row then hold halo cells,
+//     so a DPP shift that crosses from one row into the next only ever
+//     feeds halo cells).
 //   * Rows: the tile's TY output rows, (K-1)*R computed halo rows per side
 //     (stages 1..K-1 produce the values the next stage's halo needs), and R
 //     load-only rows per side that only supply stage 1's y-neighbours.
@@ -36,31 +38,31 @@ namespace star {
 
 namespace {
 
-// LDS row layout: chunk-major, [VEC/4][64 lanes][4 floats], so that every
-// 128-bit LDS access of a wavefront covers 1 KB of consecutive addresses.
-template <int VEC>
-__device__ __forceinline__ int lds_off(int lane, int chunk) {
-    return (chunk * 64 + lane) * 4;
+// LDS row layout: chunk-major, [VEC/4][WL lanes][4 floats], so that every
+// 128-bit LDS access of a row's lanes covers consecutive addresses.
+template <int VEC, int WL>
+__device__ __forceinline__ int lds_off(int lr, int chunk) {
+    return (chunk * WL + lr) * 4;
 }
 
-template <int VEC>
-__device__ __forceinline__ void lds_write_row(float *row, int lane, const float (&v)[VEC]) {
+template <int VEC, int WL>
+__device__ __forceinline__ void lds_write_row(float *row, int lr, const float (&v)[VEC]) {
 #pragma unroll
     for (int c = 0; c < VEC / 4; ++c)
-        *reinterpret_cast<float4 *>(row + lds_off<VEC>(lane, c)) =
+        *reinterpret_cast<float4 *>(row + lds_off<VEC, WL>(lr, c)) =
             make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
 }
 
-template <int VEC>
-__device__ __forceinline__ void lds_read_row(const float *row, int lane, float (&v)[VEC]) {
+template <int VEC, int WL>
+__device__ __forceinline__ void lds_read_row(const float *row, int lr, float (&v)[VEC]) {
 #pragma unroll
     for (int c = 0; c < VEC / 4; ++c) {
-        const float4 t = *reinterpret_cast<const float4 *>(row + lds_off<VEC>(lane, c));
+        const float4 t = *reinterpret_cast<const float4 *>(row + lds_off<VEC, WL>(lr, c));
         v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
     }
 }
 
-template <int R, int K, int VEC, int D, bool ALIGNED>
+template <int R, int K, int VEC, int WL, int D, bool ALIGNED>
 __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ src,
                                                       float *__restrict__ dst, int nx, int ny,
                                                       int nz, int hx, int tx, int ntx, int nty,
@@ -71,25 +73,30 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
     // Unrolled planes per loop trip: every ring index must be compile-time,
     // so the trip covers a whole number of turns of each ring.
     constexpr int U = (K == 1) ? NQ : NQ * P / gcd_i(NQ, P);
-    constexpr int W = 64 * VEC;       // columns per tile row
+    constexpr int RPW = 64 / WL;      // tile rows per wavefront
+    constexpr int W = WL * VEC;       // columns per tile row
     constexpr int ROWF = W;           // floats per LDS row
-    static_assert(R <= VEC && VEC % 4 == 0, "bad vector width");
-    extern __shared__ float lds[];    // [K][2][NW][ROWF]
+    static_assert(R <= VEC && VEC % 4 == 0 && 64 % WL == 0, "bad vector width");
+    extern __shared__ float lds[];    // [K][2][NT][ROWF]
 
     const int lane = threadIdx.x & 63;
+    const int lr = lane % WL;         // lane within its tile row
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
-    const int ty = nw - 2 * K * R;    // output rows of the tile
+    const int nt = (blockDim.x >> 6) * RPW;  // tile rows
+    const int ty = nt - 2 * K * R;    // output rows of the tile
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int strip = lb % ntx;
     const int ytile = (lb / ntx) % nty;
     const int zseg = lb / (ntx * nty);
     const int ty0 = ytile * ty;
-    const int y = ty0 - K * R + w;    // this wavefront's row
+    const int trow = w * RPW + lane / WL;  // this lane's tile row
+    const int y = ty0 - K * R + trow;      // and grid row
     const int yc = clampi(y, ny);
-    const bool load_only = (w < R) || (w >= nw - R);
-    const int xs = strip * tx - hx;   // first column held by lane 0
-    const int col0 = xs + lane * VEC;
+    // rows 0..R-1 and nt-R..nt-1 only feed stage 1; a wavefront made of
+    // such rows only loads
+    const bool load_only = (w * RPW + RPW - 1 < R) || (w * RPW >= nt - R);
+    const int xs = strip * tx - hx;   // first column held by lane 0 of a row
+    const int col0 = xs + lr * VEC;
     const int z0 = zseg * lz;
     const int z1 = min(z0 + lz, nz);
     const int zstart = z0 - K * R;
@@ -104,30 +111,37 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
 
     // LDS row of stage s (0-based), buffer b, tile row r.
     auto lds_row = [&](int s, int b, int r) STAR_INLINE -> float * {
-        return lds + ((size_t)((s * 2 + b) * nw + r)) * ROWF;
+        return lds + ((size_t)((s * 2 + b) * nt + r)) * ROWF;
     };
     // Tile row holding grid row clamp(yy) (clamped into the tile as well).
     auto tile_row = [&](int yy) STAR_INLINE -> int {
         const int r = clampi(yy, ny) - (ty0 - K * R);
-        return r < 0 ? 0 : (r >= nw ? nw - 1 : r);
+        return r < 0 ? 0 : (r >= nt ? nt - 1 : r);
+    };
+    // Value of v in lane `l` of this lane's tile row.
+    auto row_value = [&](float v, int l) STAR_INLINE -> float {
+        float b = lane_value(v, l);
+#pragma unroll
+        for (int k = 1; k < RPW; ++k) b = (lane / WL == k) ? lane_value(v, k * WL + l) : b;
+        return b;
     };
 
     auto xfix = [&](float (&v)[VEC]) STAR_INLINE {
         if (left_edge) {
             const int l0 = (-xs) / VEC;
-            const float b = lane_value(v[0], l0);
-            if (lane < l0) {
+            const float b = row_value(v[0], l0);
+            if (lr < l0) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) v[e] = b;
             }
         }
         if (right_edge) {
             const int off = nx - 1 - xs;
-            const int lr = off / VEC, er = off % VEC;
+            const int lrr = off / VEC, er = off % VEC;
             float t = v[0];
 #pragma unroll
             for (int e = 1; e < VEC; ++e) t = (er == e) ? v[e] : t;
-            const float b = lane_value(t, lr);
+            const float b = row_value(t, lrr);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[e] = (col0 + e >= nx) ? b : v[e];
         }
@@ -169,8 +183,8 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
             // once (register pressure at large R)
             if (i > 1) __builtin_amdgcn_sched_barrier(0);
             float sv[VEC], nv[VEC];
-            lds_read_row<VEC>(lds_row(s, b, tile_row(y - i)), lane, sv);
-            lds_read_row<VEC>(lds_row(s, b, tile_row(y + i)), lane, nv);
+            lds_read_row<VEC, WL>(lds_row(s, b, tile_row(y - i)), lr, sv);
+            lds_read_row<VEC, WL>(lds_row(s, b, tile_row(y + i)), lr, nv);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const float wv = (e - i >= 0) ? q[CS][e - i] : left[i - e];
@@ -212,11 +226,11 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
         load_plane(zl + DIST, q0[(PH + DIST) % NQ]);
         if constexpr (ALIGNED) xfix(q0[PH]);
         // centre planes of every stage into LDS
-        lds_write_row<VEC>(lds_row(0, b, w), lane, q0[(PH - R + NQ) % NQ]);
+        lds_write_row<VEC, WL>(lds_row(0, b, trow), lr, q0[(PH - R + NQ) % NQ]);
         if (!load_only) {
             static_for<2, K + 1>([&](auto sc) STAR_INLINE {
                 constexpr int S = decltype(sc)::value;
-                lds_write_row<VEC>(lds_row(S - 1, b, w), lane, q[S - 2][(PS - R + P) % P]);
+                lds_write_row<VEC, WL>(lds_row(S - 1, b, trow), lr, q[S - 2][(PS - R + P) % P]);
             });
         }
         __syncthreads();
@@ -286,23 +300,25 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
 // Prefetch depth (planes) per configuration, sized so that a 1024-thread
 // workgroup stays within 128 VGPRs per lane: deep for K = 1 (memory bound),
 // one window (D = P) for K > 1 so the unroll stays 2P.
-template <int K, int VEC>
+template <int K, int VEC, int WL>
 constexpr int prefetch3() {
     constexpr int P = 2 * STAR_R + 1;
     if constexpr (K > 1) return P;
+    if constexpr (VEC == 4 && WL == 32) return P + 3 > 12 ? 3 : 12 - P;  // two rows per wave
     if constexpr (VEC == 4) return P + 4 > 12 ? 4 : 12 - P;  // ring of max(12, P + 4) planes
     return 8 - P > 2 ? 8 - P : 2;                            // ring of max(8, P + 2) planes
 }
 
-template <int K, int VEC, bool AL>
+template <int K, int VEC, int WL, bool AL>
 hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
     constexpr int R = STAR_R;
-    constexpr int W = 64 * VEC;
+    constexpr int W = WL * VEC;
     const int nw = a.nw;
-    const int ty = nw - 2 * K * R;
-    if (ty < 1 || nw > 16 || nw < 2 * R) return hipErrorInvalidValue;
+    const int nt = nw * (64 / WL);
+    const int ty = nt - 2 * K * R;
+    if (ty < 1 || nw > 16 || nw < 1) return hipErrorInvalidValue;
     int hx = 0, tx = a.nx, ntx = 1;
-    if (a.nx > W) {
+    if (a.nx > W || WL != 64) {
         hx = (K * R + VEC - 1) / VEC * VEC;
         tx = W - 2 * hx;
         ntx = (a.nx + tx - 1) / tx;
@@ -311,9 +327,9 @@ hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
     const int nseg = (a.nz + a.lz - 1) / a.lz;
     const int64_t blocks = (int64_t)ntx * nty * nseg;
     if (blocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)K * 2 * nw * W * sizeof(float);
+    const size_t lds = (size_t)K * 2 * nt * W * sizeof(float);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    auto kern = star3d_stream<R, K, VEC, prefetch3<K, VEC>(), AL>;
+    auto kern = star3d_stream<R, K, VEC, WL, prefetch3<K, VEC, WL>(), AL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -327,11 +343,14 @@ hipError_t launch_kv(const Star3DArgs &a, hipStream_t stream) {
     if constexpr (K > max_k3d(STAR_R)) {
         return hipErrorInvalidValue;
     } else {
-        if (a.vec == 4) return a.aligned ? launch_k3<K, 4, true>(a, stream) : launch_k3<K, 4, false>(a, stream);
+        if (a.vec == 4 && a.wl == 64)
+            return a.aligned ? launch_k3<K, 4, 64, true>(a, stream) : launch_k3<K, 4, 64, false>(a, stream);
+        if (a.vec == 4 && a.wl == 32)
+            return a.aligned ? launch_k3<K, 4, 32, true>(a, stream) : launch_k3<K, 4, 32, false>(a, stream);
         if constexpr (K == 1 && STAR_R <= 2) {
             // a 512-column row per wavefront: only the aligned single-step
             // pass of radius <= 2 fits in the register budget
-            if (a.vec == 8 && a.aligned) return launch_k3<K, 8, true>(a, stream);
+            if (a.vec == 8 && a.wl == 64 && a.aligned) return launch_k3<K, 8, 64, true>(a, stream);
         }
         return hipErrorInvalidValue;
     }

@@ -1,0 +1,173 @@
+// tune.cpp -- measured autotuning of a plan and its on-disk cache.
+//
+// The paper picks its FPGA knobs (block size, vector width, temporal
+// degree) with an analytic model and then builds the top candidates
+// (Sec. V.A).  Here every feasible kernel configuration is timed on the
+// real grid instead, and the winner is cached per problem.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "plan.hpp"
+#include "stencil.h"
+
+using namespace star;
+
+namespace {
+
+std::mutex g_cache_mu;
+
+std::string cache_key(const stencil_plan_s *p) {
+    char buf[160];
+    hipDeviceProp_t prop;
+    const char *arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    snprintf(buf, sizeof buf, "ndim=%d R=%d storage=%d dims=%lldx%lldx%lld arch=%s", p->ndim,
+             p->radius, p->storage, (long long)p->nx, (long long)p->ny, (long long)p->nz, arch);
+    // keep only the architecture's base name (drop feature suffixes)
+    std::string k(buf);
+    const size_t colon = k.find(':', k.find("arch="));
+    if (colon != std::string::npos) k.resize(colon);
+    return k;
+}
+
+// Every configuration worth timing for this problem.
+std::vector<std::string> candidates(const stencil_plan_s *p) {
+    std::vector<std::string> out;
+    const int R = p->radius;
+    char buf[96];
+    if (p->ndim == 2) {
+        for (int K = 1; K <= max_k2d(R); ++K)
+            for (int ly : {64, 96, 128, 192, 256, 384}) {
+                if (ly > p->ny && ly != 64) continue;
+                snprintf(buf, sizeof buf, "k=%d,ly=%d", K, ly);
+                out.push_back(buf);
+            }
+    } else {
+        for (int K = 1; K <= max_k3d(R); ++K)
+            for (int wl : {64, 32})
+                for (int vec : {4, 8}) {
+                    if (vec == 8 && (wl != 64 || !vec8_ok(R, K, p->nx % 4 == 0) || p->nx <= 256))
+                        continue;
+                    for (int lz : {32, 64, 128}) {
+                        if (lz > p->nz && lz != 32) continue;
+                        snprintf(buf, sizeof buf, "k=%d,wl=%d,vec=%d,lz=%d", K, wl, vec, lz);
+                        out.push_back(buf);
+                    }
+                }
+    }
+    return out;
+}
+
+}  // namespace
+
+bool tune_cache_lookup(const stencil_plan_s *p, std::string &config) {
+    const char *path = getenv("STENCIL_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    const std::string key = cache_key(p);
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        std::string s(line);
+        while (!s.empty() && (s.back() == '\n' || s.back() == '\r')) s.pop_back();
+        const size_t t1 = s.find('\t');
+        if (t1 == std::string::npos || s.compare(0, t1, key) != 0 || t1 != key.size()) continue;
+        const size_t t2 = s.find('\t', t1 + 1);
+        config = s.substr(t1 + 1, t2 == std::string::npos ? std::string::npos : t2 - t1 - 1);
+        found = true;  // the last matching line wins
+    }
+    fclose(f);
+    return found;
+}
+
+static void tune_cache_store(const stencil_plan_s *p, const std::string &config, double gcells) {
+    const char *path = getenv("STENCIL_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s\t%s\t%.2f\n", cache_key(p).c_str(), config.c_str(), gcells);
+    fclose(f);
+}
+
+extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float *out, char *report,
+                                     size_t report_len, void *stream) {
+    if (!plan || !in || !out) return star_set_error(STENCIL_EINVAL, "plan/in/out is NULL");
+    const size_t bytes = (size_t)plan->ncells * sizeof(float);
+    {
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        if (a < b + bytes && b < a + bytes) return star_set_error(STENCIL_EINVAL, "in and out overlap");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const stencil_plan_s saved = *plan;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return star_set_error(STENCIL_EDEVICE, "hipEventCreate failed");
+    struct Result {
+        std::string config;
+        double gcells;
+    };
+    std::vector<Result> results;
+    for (const std::string &cand : candidates(plan)) {
+        stencil_plan_s trial = saved;
+        trial.scratch = saved.scratch;
+        if (plan_configure(&trial, cand.c_str()) != STENCIL_OK) continue;
+        const int K = trial.K;
+        auto time_run = [&](int64_t n, float *ms) {
+            return hipEventRecord(e0, st) == hipSuccess &&
+                   plan_enqueue(&trial, in, out, n, st) == hipSuccess &&
+                   hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                   hipEventElapsedTime(ms, e0, e1) == hipSuccess && *ms > 0.0f;
+        };
+        // warm-up, then a run scaled to last a few milliseconds
+        int64_t steps = 4 * K;
+        float ms = 0.0f;
+        if (plan_enqueue(&trial, in, out, 2 * K, st) != hipSuccess || !time_run(steps, &ms)) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (ms < 2.0f) {
+            steps = std::max<int64_t>(K, (int64_t)(steps * 4.0f / std::max(ms, 0.01f)) / K * K);
+            if (!time_run(steps, &ms)) {
+                (void)hipGetLastError();
+                continue;
+            }
+        }
+        results.push_back({cand, (double)plan->ncells * (double)steps / (ms * 1e-3) / 1e9});
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return star_set_error(STENCIL_EDEVICE, "device error while autotuning");
+    if (results.empty()) return star_set_error(STENCIL_EDEVICE, "no configuration could be timed");
+    std::stable_sort(results.begin(), results.end(),
+                     [](const Result &a, const Result &b) { return a.gcells > b.gcells; });
+    if (plan_configure(plan, results[0].config.c_str()) != STENCIL_OK) {
+        *plan = saved;
+        return star_set_error(STENCIL_EDEVICE, "best configuration did not re-apply");
+    }
+    plan->tuned_by = "autotune";
+    tune_cache_store(plan, results[0].config, results[0].gcells);
+    if (report && report_len > 0) {
+        std::string r;
+        for (const Result &x : results) {
+            char line[160];
+            snprintf(line, sizeof line, "%s %.2f\n", x.config.c_str(), x.gcells);
+            r += line;
+        }
+        const size_t n = std::min(report_len - 1, r.size());
+        std::memcpy(report, r.data(), n);
+        report[n] = '\0';
+    }
+    return STENCIL_OK;
+}

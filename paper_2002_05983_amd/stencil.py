@@ -37,6 +37,7 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_double)]),
     "stencil_plan_describe": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "stencil_plan_autotune": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_char_p, ctypes.c_size_t, _vp]),
     "stencil_reduce_f64": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                           _vp]),
     "stencil_plan_destroy": (None, [_vp]),
@@ -141,6 +142,21 @@ class Plan:
                                          ctypes.byref(bpc)))
         return {"K": K.value, "tile": tuple(tile), "vec": vec.value,
                 "bytes_per_cell_step": bpc.value}
+
+    def autotune(self, inp, out, stream=None):
+        """Times every feasible configuration on (inp, out) and keeps the
+        fastest; returns [(config, GCell/s), ...], best first.  out is
+        overwritten."""
+        _check_grid(inp, self.ncells, "inp")
+        _check_grid(out, self.ncells, "out")
+        buf = ctypes.create_string_buffer(16384)
+        _check(load().stencil_plan_autotune(self._h, inp.data_ptr(), out.data_ptr(), buf, 16384,
+                                            _stream_ptr(stream)))
+        rows = []
+        for line in buf.value.decode().splitlines():
+            cfg, g = line.rsplit(" ", 1)
+            rows.append((cfg, float(g)))
+        return rows
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(512)

@@ -114,13 +114,15 @@ def test_s3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
     f = synth.grid_uniform(800 + radius, shape)
     cache = {}
     for K in range(1, MAX_K3D[radius] + 1):
-        for nw, lz in ((16, 5), (2 * K * radius + 2, 32)):
+        for nw, lz, wl in ((16, 5, 64), (2 * K * radius + 2, 32, 64), (16, 7, 32),
+                           (K * radius + 1, 3, 32)):
             steps = 2 * K + 1
             if steps not in cache:
                 cache[steps] = oracle_mod.star_run_f32(f, c, radius, steps)
-            got, desc = gpu_run(torch, st, f, radius, c, steps, tune=f"k={K},nw={nw},lz={lz}")
+            got, desc = gpu_run(torch, st, f, radius, c, steps,
+                                tune=f"k={K},nw={nw},lz={lz},wl={wl}")
             assert "variant=s3d" in desc, desc
-            assert_bitwise(got, cache[steps], f"s3d {shape} r{radius} k{K} nw{nw} lz{lz} [{desc}]")
+            assert_bitwise(got, cache[steps], f"s3d {shape} r{radius} [{desc}]")
         if K == 1 and shape[2] % 4 == 0 and 256 < shape[2] <= 512 and radius <= 2:
             got, desc = gpu_run(torch, st, f, radius, c, 3, tune="k=1,vec=8,lz=7")
             assert "vec=8" in desc
@@ -187,3 +189,26 @@ def test_reduce_f64(torch, st, n):
     assert abs(sm - np.sum(xn)) <= 1e-12 * n
     md2, mr2, sm2 = st.reduce_f64(x, None)
     assert (md2, mr2) == (0.0, 0.0) and sm2 == sm
+
+
+@pytest.mark.parametrize("shape,radius", [((300, 700), 2), ((30, 40, 300), 1), ((20, 24, 90), 4)])
+def test_autotune_keeps_bitwise_result_and_caches(torch, st, oracle_mod, shape, radius, tmp_path,
+                                                  monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("STENCIL_TUNE_CACHE", str(cache))
+    c = synth.coefficients(950 + radius, len(shape), radius)
+    f = synth.grid_uniform(951, shape)
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    plan = st.Plan(shape, radius, c)
+    table = plan.autotune(x, y)
+    assert len(table) >= 2 and table[0][1] >= table[-1][1] > 0
+    assert "by=autotune" in plan.describe()
+    plan.run(x, y, 7)
+    torch.cuda.synchronize()
+    assert_bitwise(y.cpu().numpy(), oracle_mod.star_run_f32(f, c, radius, 7), "autotuned")
+    # a new plan of the same problem reads the cached choice
+    again = st.Plan(shape, radius, c)
+    assert "by=cache" in again.describe()
+    assert again.query()["K"] == plan.query()["K"]
+    assert table[0][0] in cache.read_text()
