@@ -111,15 +111,21 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
     for (int k = 0; k < npts; ++k) p->cf.c[k] = coeffs[k];
     p->storage = storage;
     p->anchor_m = anchor_m;
+    // the configuration is validated before any device call, so a bad
+    // request reports EINVAL even where no device is present
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
-        delete p;
-        return hip_fail(e, "hipGetDevice");
+        (void)hipGetLastError();
+        p->device = -1;
     }
     int rc = plan_configure(p, tune);
     if (rc != STENCIL_OK) {
         delete p;
         return rc;
+    }
+    if (p->device < 0) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
     }
     e = hipMalloc(&p->scratch, (size_t)ncells * sizeof(float));
     if (e != hipSuccess) {

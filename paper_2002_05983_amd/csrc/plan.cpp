@@ -117,7 +117,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 return star_set_error(STENCIL_EINVAL, ("bad tune item '" + item + "'").c_str());
             std::string key = item.substr(0, eq), val = item.substr(eq + 1);
             int v = 0;
-            if (!parse_int(val.c_str(), &v))
+            if (!parse_int(val.c_str(), &v) || v < 1)
                 return star_set_error(STENCIL_EINVAL, ("bad tune value '" + item + "'").c_str());
             if (key == "k") {
                 p->K = v;

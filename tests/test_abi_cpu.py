@@ -100,3 +100,35 @@ def test_run_and_reduce_reject_null(lib):
     assert lib.stencil_run_batched(-1, None, None, None, None, None) == -1
     assert lib.stencil_run_batched(0, None, None, None, None, None) == 0
     lib.stencil_plan_destroy(None)
+
+
+@pytest.mark.parametrize("ndim,dims,radius,tune,ok", [
+    (2, [64, 64], 1, b"k=8,ly=128", True),
+    (2, [64, 64], 4, b"k=4,ly=16", True),
+    (2, [64, 64], 4, b"k=5", False),          # K*R > 16 is not built
+    (2, [64, 64], 1, b"k=0", False),
+    (2, [64, 64], 1, b"ly=0", False),
+    (2, [64, 64], 1, b"lz=4", False),         # 3D-only key
+    (2, [64, 64], 1, b"naive", True),
+    (3, [64, 64, 64], 1, b"k=4,wl=32,lz=16", True),
+    (3, [512, 64, 64], 2, b"k=1,vec=8,wl=64", True),
+    (3, [512, 64, 64], 2, b"k=1,vec=8,wl=32", False),   # wide rows need 64 lanes
+    (3, [510, 64, 64], 1, b"k=1,vec=8,wl=64", False),   # ... and 16-byte rows
+    (3, [512, 64, 64], 3, b"k=1,vec=8,wl=64", False),   # ... and R <= 2
+    (3, [64, 64, 64], 2, b"k=3", False),
+    (3, [64, 64, 64], 4, b"k=1,nw=4,wl=64", False),     # 4 rows < 2*K*R+1
+    (3, [64, 64, 64], 4, b"k=1,nw=5,wl=32", True),
+    (3, [64, 64, 64], 1, b"wl=16", False),
+    (3, [64, 64, 64], 1, b"k=2,bogus=3", False),
+    (3, [64, 64, 64], 1, b"k=x", False),
+])
+def test_tune_strings_are_validated_before_the_device(lib, ndim, dims, radius, tune, ok):
+    c = [0.1] * (1 + 2 * ndim * radius)
+    rc, h = _plan(lib, ndim, dims, radius, c, tune=tune)
+    if ok:
+        # valid: fails only because there is no device here (or succeeds on a GPU host)
+        assert rc in (0, -3), (rc, lib.stencil_last_error())
+        if rc == 0:
+            lib.stencil_plan_destroy(h)
+    else:
+        assert rc == -1, (rc, lib.stencil_last_error())

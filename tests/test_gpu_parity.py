@@ -124,7 +124,7 @@ def test_s3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
             assert "variant=s3d" in desc, desc
             assert_bitwise(got, cache[steps], f"s3d {shape} r{radius} [{desc}]")
         if K == 1 and shape[2] % 4 == 0 and 256 < shape[2] <= 512 and radius <= 2:
-            got, desc = gpu_run(torch, st, f, radius, c, 3, tune="k=1,vec=8,lz=7")
+            got, desc = gpu_run(torch, st, f, radius, c, 3, tune="k=1,vec=8,wl=64,lz=7")
             assert "vec=8" in desc
             assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, 3), f"s3d vec8 {shape} r{radius}")
 
