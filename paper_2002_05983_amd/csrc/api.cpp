@@ -134,6 +134,13 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
         return fail(STENCIL_ENOMEM, "hipMalloc of %lld-cell scratch failed: %s", (long long)ncells,
                     hipGetErrorString(e));
     }
+    if (storage != STENCIL_F32) {
+        rc = lowp_allocate(p);
+        if (rc != STENCIL_OK) {
+            stencil_plan_destroy(p);
+            return rc;
+        }
+    }
     *plan = p;
     return STENCIL_OK;
 }
@@ -164,7 +171,16 @@ int stencil_plan_query(stencil_plan_t plan, int *K, int tile[3], int *vec,
         tile[2] = plan->tile[2];
     }
     if (vec) *vec = plan->vec;
-    if (bytes_per_cell_step) *bytes_per_cell_step = 8.0 / plan->K;
+    if (bytes_per_cell_step) {
+        if (plan->storage == STENCIL_F32) {
+            *bytes_per_cell_step = 8.0 / plan->K;
+        } else {
+            // per window of m steps: G pass 8 B, encode 6 B, m-1 delta passes of
+            // 6 B (read D and G, write D), re-anchor 10 B
+            const double m = plan->anchor_m;
+            *bytes_per_cell_step = (6.0 * m + 18.0) / m;
+        }
+    }
     return STENCIL_OK;
 }
 
@@ -189,6 +205,8 @@ int stencil_run(stencil_plan_t plan, const float *in, float *out, int64_t steps,
     if (ranges_overlap(in, out, bytes)) return fail(STENCIL_EINVAL, "in and out overlap");
     if (ranges_overlap(in, plan->scratch, bytes) || ranges_overlap(out, plan->scratch, bytes))
         return fail(STENCIL_EINVAL, "in/out overlap the plan's scratch");
+    if (plan->storage != STENCIL_F32 && ((uintptr_t)out & 15))
+        return fail(STENCIL_EINVAL, "low-precision storage needs a 16-byte aligned out");
     const hipError_t e = plan_enqueue(plan, in, out, steps, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, steps == 0 ? "hipMemcpyAsync" : "kernel launch");
     return STENCIL_OK;

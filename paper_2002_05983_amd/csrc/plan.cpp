@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "launch.hpp"
 #include "stencil.h"
@@ -67,6 +68,8 @@ bool parse_int(const char *s, int *out) {
 static int plan_apply(stencil_plan_s *p, const char *tune);
 
 int plan_configure(stencil_plan_s *p, const char *tune) {
+    if (p->storage != STENCIL_F32 && p->ndim != 3)
+        return star_set_error(STENCIL_EUNSUPPORTED, "low-precision storage is built for 3D grids");
     if (tune && *tune) {
         const int rc = plan_apply(p, tune);
         p->tuned_by = "override";
@@ -91,7 +94,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
     } else {
         // defaults measured on a 512^3 grid
         p->variant = STAR_S3D;
-        p->K = R == 1 ? 4 : R == 2 ? 2 : 1;
+        p->K = (p->storage != STENCIL_F32) ? 1 : R == 1 ? 4 : R == 2 ? 2 : 1;
         p->vec = 0;   // chosen below from the grid width
         p->s3_rows = 16;
         p->s3_lanes = 32;
@@ -107,7 +110,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             std::string item = s.substr(pos, comma - pos);
             pos = comma + 1;
             if (item.empty()) continue;
-            if (item == "naive") {
+            if (item == "naive" && p->storage == STENCIL_F32) {
                 p->variant = STAR_NAIVE;
                 p->K = 1;
                 continue;
@@ -146,6 +149,12 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->tile[1] = p->ly;
         p->tile[2] = 1;
     } else if (p->variant == STAR_S3D) {
+        if (p->storage != STENCIL_F32) {
+            // the low-precision passes are single-step, 4 cells per lane
+            if (p->K != 1 || (p->vec != 0 && p->vec != 4))
+                return star_set_error(STENCIL_EINVAL, "low-precision storage runs k=1, vec=4");
+            p->vec = 4;
+        }
         if (p->K < 1 || p->K > max_k3d(R))
             return star_set_error(STENCIL_EINVAL, "3D k must be in 1..4/2/1/1 for R = 1..4");
         if (p->s3_lanes != 64 && p->s3_lanes != 32)
@@ -176,6 +185,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
 
 hipError_t plan_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
                         hipStream_t stream) {
+    if (p->storage != STENCIL_F32) return lowp_enqueue(p, in, out, steps, stream);
     if (steps == 0)
         return hipMemcpyAsync(out, in, (size_t)p->ncells * sizeof(float), hipMemcpyDeviceToDevice,
                               stream);
@@ -257,9 +267,12 @@ std::string plan_describe(const stencil_plan_s *p) {
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
     if (p->variant == STAR_S3D)
         snprintf(buf, sizeof buf,
-                 "variant=s3d ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d by=%s",
+                 "variant=%s ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d%s by=%s",
+                 p->storage == STENCIL_F32 ? "s3d" : p->storage == STENCIL_F16 ? "s3d-f16" : "s3d-bf16",
                  p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_lanes,
-                 p->s3_rows, p->s3_lz, p->tuned_by.c_str());
+                 p->s3_rows, p->s3_lz,
+                 p->storage == STENCIL_F32 ? "" : (" m=" + std::to_string(p->anchor_m)).c_str(),
+                 p->tuned_by.c_str());
     else
         snprintf(buf, sizeof buf, "variant=%s ndim=%d R=%d K=%d tile=%dx%dx%d vec=%d ly=%d by=%s", v,
                  p->ndim, p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->ly,
@@ -267,4 +280,4 @@ std::string plan_describe(const stencil_plan_s *p) {
     return buf;
 }
 
-void plan_release_extra(stencil_plan_s *) {}
+void plan_release_extra(stencil_plan_s *p) { lowp_release(p); }

@@ -15,6 +15,8 @@ enum star_variant : int {
     STAR_S3D = 2,    // 3D xy-tile in LDS / z-stream, K fused steps
 };
 
+struct LowpState;  // precision-form buffers (lowp.cpp)
+
 struct stencil_plan_s {
     // problem
     int ndim = 2;
@@ -25,7 +27,8 @@ struct stencil_plan_s {
     int storage = 0;
     int anchor_m = 0;
     int device = 0;
-    float *scratch = nullptr;  // one FP32 grid, ping-pong partner of `out`
+    float *scratch = nullptr;  // one FP32 grid, ping-pong partner of `out` (the anchor for F16/BF16)
+    LowpState *lowp = nullptr; // low-precision state when storage != F32
 
     // configuration
     int variant = STAR_NAIVE;
@@ -55,6 +58,12 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
                             hipStream_t stream);
 std::string plan_describe(const stencil_plan_s *p);
 void plan_release_extra(stencil_plan_s *p);
+
+// Precision form (lowp.cpp): device state, and the run schedule.
+int lowp_allocate(stencil_plan_s *p);
+void lowp_release(stencil_plan_s *p);
+hipError_t lowp_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
+                        hipStream_t stream);
 
 // Records a failure for stencil_last_error() and returns status.
 int star_set_error(int status, const char *msg);

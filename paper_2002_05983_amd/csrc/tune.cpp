@@ -51,10 +51,12 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                 out.push_back(buf);
             }
     } else {
-        for (int K = 1; K <= max_k3d(R); ++K)
+        const int kmax = p->storage == STENCIL_F32 ? max_k3d(R) : 1;
+        for (int K = 1; K <= kmax; ++K)
             for (int wl : {64, 32})
                 for (int vec : {4, 8}) {
-                    if (vec == 8 && (wl != 64 || !vec8_ok(R, K, p->nx % 4 == 0) || p->nx <= 256))
+                    if (vec == 8 && (wl != 64 || !vec8_ok(R, K, p->nx % 4 == 0) || p->nx <= 256 ||
+                                     p->storage != STENCIL_F32))
                         continue;
                     for (int lz : {32, 64, 128}) {
                         if (lz > p->nz && lz != 32) continue;

@@ -212,3 +212,42 @@ def test_autotune_keeps_bitwise_result_and_caches(torch, st, oracle_mod, shape, 
     assert "by=cache" in again.describe()
     assert again.query()["K"] == plan.query()["K"]
     assert table[0][0] in cache.read_text()
+
+
+# precision form: bitwise against the CPU model of the same algorithm
+LOWP_SHAPES = [(70, 68, 136), (9, 70, 72), (66, 5, 300)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", LOWP_SHAPES)
+def test_precision_form_matches_model_bitwise(torch, st, radius, shape):
+    from oracle import precision
+    c = synth.coefficients(1100 + radius, 3, radius)
+    f = synth.sinusoid_grid(1200 + radius, max(shape), modes=4)[:shape[0], :shape[1], :shape[2]].copy()
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    for storage, codec in (("f16", precision.F16), ("bf16", precision.BF16)):
+        for m, steps, tune in ((3, 7, "wl=64,lz=16"), (7, 7, "wl=32,lz=40"), (1, 2, None)):
+            plan = st.Plan(shape, radius, c, storage=storage, anchor_m=m, tune=tune)
+            plan.run(x, y, steps)
+            torch.cuda.synchronize()
+            want = precision.run(f, c, radius, steps, m, codec)
+            assert_bitwise(y.cpu().numpy(), want, f"{storage} m{m} {shape} r{radius} [{plan.describe()}]")
+            plan.close()
+
+
+def test_precision_form_error_and_speed_report(torch, st, oracle_mod):
+    """Small sinusoid field: FP16/BF16 error against FP64 stays in the model's range."""
+    shape = (64, 64, 128)
+    c = synth.coefficients(1300, 3, 4)
+    f = synth.sinusoid_grid(1301, 128, modes=8)[:64, :64, :].copy()
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    ref = oracle_mod.star_run_f64(f, c, 4, 30)
+    for storage, m, tol in (("f16", 10, 1e-3), ("f16", 50, 1e-3), ("bf16", 10, 1e-2)):
+        plan = st.Plan(shape, 4, c, storage=storage, anchor_m=m)
+        plan.run(x, y, 30)
+        torch.cuda.synchronize()
+        err = oracle_mod.rel_linf(y.cpu().numpy(), ref)
+        assert err <= tol, (storage, m, err)
+        plan.close()
