@@ -70,6 +70,11 @@ constexpr int kOutOfRange = (int)0x80000000u;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, int bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, kRsrcWord3);
 }
+// Byte offset `off` (< 2^31) when `ok`, else an out-of-range offset: the top
+// bit is or-ed in, so the store stays one unconditional instruction.
+__device__ __forceinline__ int masked_offset(int off, bool ok) {
+    return (int)((unsigned)off | ((unsigned)(!ok) << 31));
+}
 __device__ __forceinline__ void buffer_store4(__amdgpu_buffer_rsrc_t r, int off, float a, float b,
                                               float c, float d) {
     const v4i v = {__builtin_bit_cast(int, a), __builtin_bit_cast(int, b),

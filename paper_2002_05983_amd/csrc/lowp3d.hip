@@ -130,18 +130,29 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         const size_t off = (size_t)clampi(zz, nz) * plane + (size_t)yc * nx + cl;
         v = *reinterpret_cast<const uint2 *>(a.g + off);
     };
-    // per-tile exponent of a table, cached for the current z-tile
-    struct ECache {
-        int tz = -1;
-        int e = 0;
-    };
-    auto exponent = [&](const int *tab, ECache &c, int zz) STAR_INLINE -> int {
-        const int tz = clampi(zz, nz) >> kTileShift;
-        if (tz != c.tz) {
-            c.tz = tz;
-            c.e = tab[tile_xy + tz * tile_zstride];
+    // Exponents of the storage tiles this block touches, staged in LDS once
+    // (no global load inside the plane loop, so the memory counters only
+    // ever wait for the data rings).  Tables: 0 = input D, 1 = G, 2 = output.
+    const int ptx0 = max(xs, 0) >> kTileShift, ptx1 = min(xs + W - 1, nx - 1) >> kTileShift;
+    const int pty0 = clampi(ty0 - R, ny) >> kTileShift;
+    const int pty1 = clampi(ty0 - R + nt - 1, ny) >> kTileShift;
+    const int ptz0 = clampi(zstart, nz) >> kTileShift, ptz1 = clampi(zlast + NR, nz) >> kTileShift;
+    const int enx = ptx1 - ptx0 + 1, eny = pty1 - pty0 + 1, enz = ptz1 - ptz0 + 1;
+    const int ecount = enx * eny * enz;  // <= 5 * 2 * (lz/64 + 3)
+    int *etab = reinterpret_cast<int *>(lds + (size_t)2 * nt * W);
+    if constexpr (!FP32_IN) {
+        for (int i = threadIdx.x; i < 3 * ecount; i += blockDim.x) {
+            const int tbl = i / ecount, k = i % ecount;
+            const int gx = ptx0 + k % enx, gy = pty0 + (k / enx) % eny, gz = ptz0 + k / (enx * eny);
+            const int *src_tab = tbl == 0 ? a.e_in : tbl == 1 ? a.e_g : a.e_out;
+            etab[i] = src_tab[(gz * a.tny + gy) * a.tnx + gx];
         }
-        return c.e;
+        __syncthreads();
+    }
+    const int exy = ((yc >> kTileShift) - pty0) * enx + ((cl >> kTileShift) - ptx0);
+    auto exponent = [&](int tbl, int zz) STAR_INLINE -> int {
+        const int tz = (clampi(zz, nz) >> kTileShift) - ptz0;
+        return etab[tbl * ecount + tz * enx * eny + exy];
     };
     auto decode4 = [&](const uint2 &q, int e, float (&v)[VEC]) STAR_INLINE {
         v[0] = decode_code<MODE>(q.x & 0xFFFFu, e);
@@ -157,16 +168,13 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) win[p][e] = 0.0f;
-    ECache ce_in, ce_g, ce_out;
-    float runmax = 0.0f;
-    int run_tz = -1;
-    auto flush_max = [&]() STAR_INLINE {
-        if (run_tz >= 0 && row_out && col0 >= out_lo && col0 + VEC <= out_hi)
-            atomicMax(a.max_out + tile_xy + run_tz * tile_zstride, __float_as_uint(runmax));
-        runmax = 0.0f;
-    };
+    // z-segments are exactly one 64-plane storage tile (the launcher fixes
+    // lz = 64), so a lane's running maximum covers one output tile and is
+    // published once, after the plane loop.
+    float runmax = 0.0f, runmax_all = 0.0f;
 
-    static_for<0, NR>([&](auto phc) STAR_INLINE {
+    // NR-1 planes ahead; the last slot is filled by the first iteration
+    static_for<0, NR - 1>([&](auto phc) STAR_INLINE {
         constexpr int PH = decltype(phc)::value;
         load_raw(zstart + PH, raw[PH]);
         if constexpr (!FP32_IN) load_g(zstart - R + PH, graw[PH]);
@@ -178,23 +186,29 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         const int zl = zstart + n;  // plane entering the window
         const int r = zl - R;       // plane produced
         const int b = n & 1;
-        // decode the entering plane, then reuse its ring slot for plane zl+P
-        if constexpr (FP32_IN) {
-            win[PH][0] = raw[QH].x; win[PH][1] = raw[QH].y;
-            win[PH][2] = raw[QH].z; win[PH][3] = raw[QH].w;
-        } else {
-            decode4(raw[QH], exponent(a.e_in, ce_in, min(zl, zlast)), win[PH]);
-        }
-        load_raw(zl + NR, raw[QH]);
-        uint2 gq = {0u, 0u};
-        if constexpr (!FP32_IN) {
-            gq = graw[QH];
-            load_g(r + NR, graw[QH]);
-        }
-        xfix(win[PH]);
+        // prefetch into the slot whose plane the previous iteration consumed
+        constexpr int QN = (QH + NR - 1) % NR;
+        load_raw(zl + NR - 1, raw[QN]);
+        if constexpr (!FP32_IN) load_g(r + NR - 1, graw[QN]);
+        // the centre plane (entered the window R iterations ago) to LDS
         lds_write_row4(lds_row(b, trow), lr, win[(PH - R + P) % P]);
         __syncthreads();
-        if (load_only) return;
+        // The entering plane is first needed by this step's very last term
+        // (A_R), so it is decoded just before it: its load overlaps the rest
+        // of the step.
+        auto enter = [&]() STAR_INLINE {
+            if constexpr (FP32_IN) {
+                win[PH][0] = raw[QH].x; win[PH][1] = raw[QH].y;
+                win[PH][2] = raw[QH].z; win[PH][3] = raw[QH].w;
+            } else {
+                decode4(raw[QH], exponent(0, min(zl, zlast)), win[PH]);
+            }
+            xfix(win[PH]);
+        };
+        if (load_only) {
+            enter();
+            return;
+        }
         constexpr int CS = (PH - R + P) % P;
         float left[R + 1], right[R + 1];
 #pragma unroll
@@ -220,15 +234,15 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
                 acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kS, i)], sv[e], acc[e]);
                 acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kN, i)], nv[e], acc[e]);
                 acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kB, i)], win[(CS - i + P) % P][e], acc[e]);
-                acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kA, i)], win[(CS + i) % P][e], acc[e]);
+                if (i < R)
+                    acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kA, i)], win[(CS + i) % P][e], acc[e]);
             }
         }
+        enter();  // win[(CS + R) % P] is the entering plane
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kA, R)], win[(CS + R) % P][e], acc[e]);
         const bool ok = row_out && r >= z0 && r < z1 && col0 >= out_lo && col0 + VEC <= out_hi;
-        const int tz = clampi(r, nz) >> kTileShift;
-        if (r >= z0 && tz != run_tz) {
-            flush_max();
-            run_tz = tz;
-        }
         if constexpr (FP32_IN) {
             // G = S A - A
             float g[VEC];
@@ -237,25 +251,27 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
                 g[e] = acc[e] - win[CS][e];
                 runmax = fmaxf(runmax, fabsf(g[e]));
             }
-            const auto st = buffer_rsrc(a.g_out + (size_t)clampi(r, nz) * plane + (size_t)yc * nx,
-                                        nx * 4);
-            buffer_store4(st, ok ? col0 * 4 : kOutOfRange, g[0], g[1], g[2], g[3]);
+            // one descriptor per plane (wave-uniform); the row goes into the offset
+            const auto st = buffer_rsrc(a.g_out + (size_t)clampi(r, nz) * plane, (int)(plane * 4));
+            buffer_store4(st, masked_offset((yc * nx + col0) * 4, ok), g[0], g[1], g[2], g[3]);
         } else {
             float gv[VEC];
-            decode4(gq, exponent(a.e_g, ce_g, r), gv);
-            const int eo = exponent(a.e_out, ce_out, r);
+            decode4(graw[QH], exponent(1, r), gv);
+            const int eo = exponent(2, r);
             uint32_t q[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 q[e] = encode_code<MODE>(acc[e] + gv[e], eo);
                 runmax = fmaxf(runmax, fabsf(decode_code<MODE>(q[e], eo)));
             }
-            const auto st = buffer_rsrc(a.d_out + (size_t)clampi(r, nz) * plane + (size_t)yc * nx,
-                                        nx * 2);
+            const auto st = buffer_rsrc(a.d_out + (size_t)clampi(r, nz) * plane, (int)(plane * 2));
             const v2i packed = {(int)(q[0] | (q[1] << 16)), (int)(q[2] | (q[3] << 16))};
-            __builtin_amdgcn_raw_buffer_store_b64(packed, st, ok ? col0 * 2 : kOutOfRange, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(packed, st, masked_offset((yc * nx + col0) * 2, ok),
+                                                  0, 0);
         }
         if (!ok) runmax = 0.0f;  // only cells this lane writes count
+        runmax_all = fmaxf(runmax_all, runmax);
+        runmax = 0.0f;
     };
 
     int n0 = 0;
@@ -265,7 +281,8 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     static_for<0, U>([&](auto phc) STAR_INLINE {
         if (n0 + decltype(phc)::value < niter) step_plane(phc, n0 + decltype(phc)::value);
     });
-    if (!load_only) flush_max();
+    if (!load_only && row_out && col0 >= out_lo && col0 + VEC <= out_hi)
+        atomicMax(a.max_out + tile_xy + (z0 >> kTileShift) * tile_zstride, __float_as_uint(runmax_all));
 }
 
 template <int WL, int MODE>
@@ -284,8 +301,11 @@ hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
     const int nty = (a.ny + ty - 1) / ty;
     const int nseg = (a.nz + a.lz - 1) / a.lz;
     const int64_t blocks = (int64_t)ntx * nty * nseg;
-    const size_t lds = (size_t)2 * nt * W * sizeof(float);
+    // + the staged exponent tables: 3 tables of (W/64+1) x 2 x (lz/64+3) tiles
+    const size_t etab = (size_t)3 * (W / 64 + 1) * 2 * (a.lz / 64 + 3) * sizeof(int);
+    const size_t lds = (size_t)2 * nt * W * sizeof(float) + etab;
     if (blocks > ((int64_t)1 << 30) || lds > 160 * 1024) return hipErrorInvalidValue;
+    if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     auto kern = lowp3d_step<R, WL, MODE>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -301,7 +321,8 @@ hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
 #define STAR_CAT(a, b) STAR_CAT2(a, b)
 
 hipError_t STAR_CAT(launch_lowp3d_r, STAR_R)(const LowpArgs &a, int mode, hipStream_t stream) {
-    if (a.lz < 1 || a.nx < 4 || a.ny < 1 || a.nz < 1) return hipErrorInvalidValue;
+    // one z-segment per storage tile (the kernel publishes one maximum per lane)
+    if (a.lz != (1 << kTileShift) || a.nx < 4 || a.ny < 1 || a.nz < 1) return hipErrorInvalidValue;
     if (a.wl == 64) {
         if (mode == 0) return launch_m<64, 0>(a, stream);
         if (mode == kCodecF16) return launch_m<64, kCodecF16>(a, stream);

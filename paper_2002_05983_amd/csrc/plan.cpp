@@ -149,11 +149,14 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->tile[1] = p->ly;
         p->tile[2] = 1;
     } else if (p->variant == STAR_S3D) {
+        if (p->nx * p->ny * 4 >= ((int64_t)1 << 31))
+            return star_set_error(STENCIL_EUNSUPPORTED, "3D planes must stay below 2^31 bytes");
         if (p->storage != STENCIL_F32) {
             // the low-precision passes are single-step, 4 cells per lane
-            if (p->K != 1 || (p->vec != 0 && p->vec != 4))
-                return star_set_error(STENCIL_EINVAL, "low-precision storage runs k=1, vec=4");
+            if (p->K != 1 || (p->vec != 0 && p->vec != 4) || (p->s3_lz != 0 && p->s3_lz != 64))
+                return star_set_error(STENCIL_EINVAL, "low-precision storage runs k=1, vec=4, lz=64");
             p->vec = 4;
+            p->s3_lz = 64;  // one z-segment per 64^3 storage tile
         }
         if (p->K < 1 || p->K > max_k3d(R))
             return star_set_error(STENCIL_EINVAL, "3D k must be in 1..4/2/1/1 for R = 1..4");

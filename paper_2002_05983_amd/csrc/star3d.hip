@@ -108,6 +108,7 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
     const int out_hi = min(xs + hx + tx, nx);
     const bool row_out = y >= ty0 && y < ty0 + ty && y < ny;
     const size_t plane = (size_t)nx * (size_t)ny;
+    const int plane_bytes = (int)(plane * sizeof(float));  // < 2^31, checked by the launcher
 
     // LDS row of stage s (0-based), buffer b, tile row r.
     auto lds_row = [&](int s, int b, int r) STAR_INLINE -> float * {
@@ -264,15 +265,17 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
                         });
                     }
                 } else {
+                    // one descriptor per plane (wave-uniform); the row goes
+                    // into the per-lane offset
                     const bool ok_row = row_out && r >= z0 && r < z1;
-                    const auto rs = buffer_rsrc(
-                        dst + (size_t)clampi(r, nz) * plane + (size_t)yc * nx, nx * 4);
+                    const auto rs = buffer_rsrc(dst + (size_t)clampi(r, nz) * plane, plane_bytes);
+                    const int rowoff = yc * nx;
                     if constexpr (ALIGNED) {
 #pragma unroll
                         for (int c = 0; c < VEC / 4; ++c) {
                             const int cc = col0 + 4 * c;
                             const bool ok = ok_row && cc >= out_lo && cc + 4 <= out_hi;
-                            buffer_store4(rs, ok ? cc * 4 : kOutOfRange, res[4 * c],
+                            buffer_store4(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[4 * c],
                                           res[4 * c + 1], res[4 * c + 2], res[4 * c + 3]);
                         }
                     } else {
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
                         for (int e = 0; e < VEC; ++e) {
                             const int cc = col0 + e;
                             const bool ok = ok_row && cc >= out_lo && cc < out_hi;
-                            buffer_store1(rs, ok ? cc * 4 : kOutOfRange, res[e]);
+                            buffer_store1(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[e]);
                         }
                     }
                 }
@@ -327,6 +330,7 @@ hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
     const int nseg = (a.nz + a.lz - 1) / a.lz;
     const int64_t blocks = (int64_t)ntx * nty * nseg;
     if (blocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+    if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const size_t lds = (size_t)K * 2 * nt * W * sizeof(float);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     auto kern = star3d_stream<R, K, VEC, WL, prefetch3<K, VEC, WL>(), AL>;

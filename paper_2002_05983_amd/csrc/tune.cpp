@@ -60,6 +60,7 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                         continue;
                     for (int lz : {32, 64, 128}) {
                         if (lz > p->nz && lz != 32) continue;
+                        if (p->storage != STENCIL_F32 && lz != 64) continue;
                         snprintf(buf, sizeof buf, "k=%d,wl=%d,vec=%d,lz=%d", K, wl, vec, lz);
                         out.push_back(buf);
                     }

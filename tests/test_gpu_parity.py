@@ -227,7 +227,7 @@ def test_precision_form_matches_model_bitwise(torch, st, radius, shape):
     x = torch.from_numpy(f).cuda()
     y = torch.empty_like(x)
     for storage, codec in (("f16", precision.F16), ("bf16", precision.BF16)):
-        for m, steps, tune in ((3, 7, "wl=64,lz=16"), (7, 7, "wl=32,lz=40"), (1, 2, None)):
+        for m, steps, tune in ((3, 7, "wl=64"), (7, 7, "wl=32,nw=12"), (1, 2, None)):
             plan = st.Plan(shape, radius, c, storage=storage, anchor_m=m, tune=tune)
             plan.run(x, y, steps)
             torch.cuda.synchronize()
