@@ -9,9 +9,12 @@ before timing starts.  Prints one JSON line.
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-tune] [--no-3d]
 
 Each plan is autotuned (every feasible kernel configuration timed at the
-real shape) before the timed region.  A secondary leg measures the 3D
-workload (512^3, radius 1..4, 200 steps each) the same way and reports it
-under "extra".
+real shape) before the timed region.  Secondary legs, reported under
+"extra": the 3D workload (512^3, radius 1..4, 200 steps each) measured the
+same way; the precision form (768^3 radius 4, 1000 steps, FP32 against
+FP16/BF16 storage re-anchored every 10 or 50 steps, with errors); and the
+batched form (256 mixed 2D/3D grids, 100 steps, one captured batch against
+256 single-grid runs).
 
 value: whole-job cell updates per second (GCell/s, Eq. (3) of the paper read
 as cells*iterations/time), summed over the four radii.
@@ -40,6 +43,43 @@ PEAK_FP32_TFLOPS = 157.3
 SIDE = 16384
 TIME_STEPS = 1000
 RADII = (1, 2, 3, 4)
+
+
+# HBM traffic of the dominant 2D kernel from rocprofv3 counters (FETCH_SIZE
+# and WRITE_SIZE, separate runs, each scaled by its reading for a plain copy
+# of known size).  Used only while the kernel's sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "star2d_stream_16384sq_pmc_traffic.txt")
+KERNEL_SOURCES = ("star2d.hip", "star2d_body.hpp", "common.hpp", "launch.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2002_05983_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """Counter-measured HBM bytes per launch of `kernel`, or None when the
+    record is missing, for another configuration, or older than the source."""
+    try:
+        rec = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    rec[k.strip()] = v.strip()
+        if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def flop_per_cell(ndim: int, radius: int) -> int:
@@ -98,6 +138,149 @@ def bench_3d(stencil, synth, torch, dev, side=512, time_steps=200, reps=2, tune=
                         f"radius, clamp", "GCell/s": round(total, 1), "per_radius": rows}
 
 
+def read_precision_reference():
+    """FP64 oracle values of the reduced precision workload (128^3, radius 4,
+    1000 steps) on sampled cells, from the fixture its generator wrote."""
+    path = os.path.join(ROOT, "tests", "golden", "precision_128cube_r4_1000.txt")
+    maxabs, cells, vals = None, [], []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# maxabs"):
+                maxabs = float(line.split()[2])
+            elif line.strip() and not line.startswith("#"):
+                x, y, z, v = line.split()
+                cells.append((int(x), int(y), int(z)))
+                vals.append(float(v))
+    return maxabs, cells, vals
+
+
+def bench_precision(stencil, synth, torch, dev, side=768, time_steps=1000, radius=4,
+                    anchors=(10, 50), reps=1):
+    """Precision form: FP32 against FP16/BF16 storage with re-anchoring every m
+    steps, 3D radius 4 on the side^3 sinusoid grid.  Error vs the FP32 run on
+    the full grid (FP64 reduction on the GPU), and vs the FP64 oracle on the
+    sampled cells of the reduced 128^3 workload."""
+    shape = (side, side, side)
+    c = synth.coefficients(3004, 3, radius)
+    x = torch.from_numpy(synth.sinusoid_grid(4, side)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    cells = x.numel()
+
+    def timed(plan, y):
+        plan.run(x, y, 2, stream=stream)  # warm-up
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(stream)
+        for _ in range(reps):
+            plan.run(x, y, time_steps, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        return a.elapsed_time(b) / reps
+
+    p32 = stencil.Plan(shape, radius, c)
+    ref = torch.empty_like(x)
+    ms32 = timed(p32, ref)
+    gc32 = cells * time_steps / (ms32 / 1e3) / 1e9
+    rows = [{"storage": "f32", "m": None, "ms": round(ms32, 2), "GCell/s": round(gc32, 1),
+             "config": p32.describe()}]
+    ref64 = ref.double()
+    y = torch.empty_like(x)
+    for storage in ("f16", "bf16"):
+        for m in anchors:
+            p = stencil.Plan(shape, radius, c, storage=storage, anchor_m=m)
+            ms = timed(p, y)
+            md, mr, _ = stencil.reduce_f64(y, ref64, stream=stream)
+            gc = cells * time_steps / (ms / 1e3) / 1e9
+            rows.append({"storage": storage, "m": m, "ms": round(ms, 2), "GCell/s": round(gc, 1),
+                         "speedup_vs_f32": round(gc / gc32, 3), "rel_linf_vs_f32": md / mr})
+            p.close()
+    del ref64, y, ref, x
+    torch.cuda.empty_cache()
+    # error against the FP64 oracle: reduced workload, stored sampled values
+    maxabs, pts, want = read_precision_reference()
+    n = 128
+    xs = torch.from_numpy(synth.sinusoid_grid(4, n)).to(dev)
+    ys = torch.empty_like(xs)
+    idx = torch.tensor([(z * n + yy) * n + xx for xx, yy, z in pts], device=dev)
+    wantt = torch.tensor(want, dtype=torch.float64, device=dev)
+    fp64 = {}
+    for storage, m in [("f32", 0)] + [(s_, m_) for s_ in ("f16", "bf16") for m_ in anchors]:
+        p = stencil.Plan((n, n, n), radius, c, storage=storage, anchor_m=m)
+        p.run(xs, ys, time_steps, stream=stream)
+        got = ys.view(-1)[idx].double()
+        err = float((got - wantt).abs().max()) / maxabs
+        fp64[storage if storage == "f32" else f"{storage}_m{m}"] = err
+        p.close()
+    for r in rows:
+        key = r["storage"] if r["storage"] == "f32" else f"{r['storage']}_m{r['m']}"
+        r["rel_linf_vs_fp64_128cube_sampled"] = fp64[key]
+    p32.close()
+    return {"workload": f"precision form: 3D star r={radius} on {side}^3 seeded sinusoid grid "
+                        f"(8 modes + 1e-3 noise), {time_steps} steps, FP32 vs FP16/BF16 storage "
+                        f"with per-64^3-tile power-of-two scales, FP32 re-anchor every m steps",
+            "fp64_error_workload": f"{n}^3, same recipe, {time_steps} steps, FP64 oracle on "
+                                   f"{len(pts)} stored cells (8 corners + 248 drawn)",
+            "rows": rows}
+
+
+def bench_batch(stencil, synth, torch, dev, time_steps=100, reps=3, tune=True):
+    """Batched form: 256 grids (128 2D with sides log-uniform in 64..4096,
+    128 3D with sides log-uniform in 32..256, radius uniform in 1..4, U[0,1)
+    values, seeded coefficients), 100 steps each, as one captured batch,
+    against 256 separate stencil_run calls on the same stream."""
+    shapes = synth.batch_shapes(5)
+    stream = torch.cuda.current_stream(dev)
+    plans, ins, outs, refs = [], [], [], []
+    flop = 0
+    for dims, radius, cseed, vseed in shapes:
+        shape = tuple(reversed(dims))
+        p = stencil.Plan(shape, radius, synth.coefficients(cseed, len(shape), radius))
+        x = torch.from_numpy(synth.grid_uniform(vseed, shape)).to(dev)
+        plans.append(p)
+        ins.append(x)
+        outs.append(torch.empty_like(x))
+        refs.append(torch.empty_like(x))
+        flop += x.numel() * time_steps * flop_per_cell(len(shape), radius)
+    cells = sum(x.numel() for x in ins)
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        return a.elapsed_time(b) / reps
+
+    def per_grid():
+        for p, x, r in zip(plans, ins, refs):
+            p.run(x, r, time_steps, stream=stream)
+
+    ms_pg = timed(per_grid)
+    batch = stencil.Batch(plans, ins, outs, time_steps)
+    if tune:
+        batch.autotune(stream=stream)
+    ms_b = timed(lambda: batch.launch(stream=stream))
+    equal = all(torch.equal(o, r) for o, r in zip(outs, refs))
+    desc = batch.describe()
+    batch.close()
+    for p in plans:
+        p.close()
+    gc = cells * time_steps / (ms_b / 1e3) / 1e9
+    return {"workload": "256 grids: 128 2D (sides log-uniform 64..4096) + 128 3D (sides "
+                        "log-uniform 32..256), radius uniform 1..4, FP32 U[0,1), seeded "
+                        f"coefficients, {time_steps} steps each",
+            "cells": cells, "ms": round(ms_b, 2), "GCell/s": round(gc, 1),
+            "GFLOP/s": round(flop / (ms_b / 1e3) / 1e9, 1),
+            "per_grid_ms": round(ms_pg, 2),
+            "per_grid_GCell/s": round(cells * time_steps / (ms_pg / 1e3) / 1e9, 1),
+            "speedup_vs_per_grid": round(ms_pg / ms_b, 2),
+            "bitwise_equal_to_per_grid": bool(equal),
+            "schedule": desc.splitlines()[0]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,7 +289,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the plans' default configurations")
     ap.add_argument("--no-3d", action="store_true", help="skip the secondary 3D leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-form leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
+    ap.add_argument("--time-steps", type=int, default=TIME_STEPS, help=argparse.SUPPRESS)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB FP32 buffer 4 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -120,6 +308,17 @@ def main():
     from paper_2002_05983_amd import stencil, synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # a plain device copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 28, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize(dev)
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 1 << 30,
+                          "bytes_written_per_launch": 1 << 30, "launches": 4}), flush=True)
+        return
+    time_steps = args.time_steps
     side = args.side
     shape = (side, side)
     f0 = synth.grid_uniform(1, shape)
@@ -131,12 +330,13 @@ def main():
     if not args.no_tune:
         for r in RADII:
             plans[r].autotune(x, y, stream=stream)
+            progress(f"2D radius {r} tuned: {plans[r].describe()}")
 
     def one_step(record=None):
         for r in RADII:
             if record is not None:
                 record[r][0].record(stream)
-            plans[r].run(x, y, TIME_STEPS, stream=stream)
+            plans[r].run(x, y, time_steps, stream=stream)
             if record is not None:
                 record[r][1].record(stream)
 
@@ -157,7 +357,7 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / args.steps
     cells = side * side
-    updates_per_step = cells * TIME_STEPS * len(RADII)
+    updates_per_step = cells * time_steps * len(RADII)
     value = updates_per_step * args.steps / (total_ms / 1e3) / 1e9
 
     per_radius = []
@@ -166,8 +366,8 @@ def main():
         ms = sum(ev[r][0].elapsed_time(ev[r][1]) for ev in events) / args.steps
         q = plans[r].query()
         K = q["K"]
-        npass = -(-TIME_STEPS // K)
-        gc = cells * TIME_STEPS / (ms / 1e3) / 1e9
+        npass = -(-time_steps // K)
+        gc = cells * time_steps / (ms / 1e3) / 1e9
         row = {"radius": r, "K": K, "tile": q["tile"][:2], "ms": round(ms, 3),
                "GCell/s": round(gc, 1), "GFLOP/s": round(gc * flop_per_cell(2, r), 1),
                "eff_GB/s": round(gc * 8, 1), "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
@@ -181,13 +381,17 @@ def main():
     hbm_gbs = cells * 8 / launch_s / 1e9
     alu_tflops = cells * K * flop_per_cell(2, r) / launch_s / 1e12
     hbm_frac, alu_frac = hbm_gbs / PEAK_HBM_GBS, alu_tflops / PEAK_FP32_TFLOPS
+    kernel = f"star2d_stream R={r} K={K} ly={dominant['tile'][1]} grid={side}x{side}"
+    traffic = measured_traffic(kernel)
     if hbm_frac >= alu_frac:
         roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
+                    "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": traffic}
     else:
         roofline = {"bound": "alu", "achieved": round(alu_tflops, 2), "peak": PEAK_FP32_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": None}
-    roofline["kernel"] = f"star2d_stream R={r} K={K}"
+                    "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": traffic}
+    roofline["kernel"] = kernel
+    roofline["algorithmic_bytes_per_launch"] = cells * 8
+    roofline["source_sha256"] = kernel_source_hash()
     roofline["other"] = {"hbm_GB/s": round(hbm_gbs, 1), "hbm_frac": round(hbm_frac, 4),
                          "alu_TFLOP/s": round(alu_tflops, 2), "alu_frac": round(alu_frac, 4)}
 
@@ -206,8 +410,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D star stencils r=1..4, {side}x{side} FP32 grid U[0,1), "
                                f"seeded coefficients summing to 1, clamp boundary, "
-                               f"{TIME_STEPS} steps per radius, temporal degree per plan",
-                   "radii": list(RADII), "grid": [side, side], "time_steps": TIME_STEPS},
+                               f"{time_steps} steps per radius, temporal degree per plan",
+                   "radii": list(RADII), "grid": [side, side], "time_steps": time_steps},
         "gflops": round(sum(p["GFLOP/s"] * p["ms"] for p in per_radius) /
                         sum(p["ms"] for p in per_radius), 1),
         "per_radius": per_radius,
@@ -217,10 +421,22 @@ def main():
         p.close()
     del x, y
     torch.cuda.empty_cache()
+    progress(f"2D: {value:.1f} GCell/s")
+    extra = {}
     if not args.no_3d:
-        out["extra"] = {"3d": bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)}
+        extra["3d"] = bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)
+        progress(f"3D: {extra['3d']['GCell/s']} GCell/s")
+    if not args.no_precision:
+        extra["precision"] = bench_precision(stencil, synth, torch, dev)
+        progress("precision form done")
+    if not args.no_batch:
+        extra["batch"] = bench_batch(stencil, synth, torch, dev, tune=not args.no_tune)
+        progress(f"batch: {extra['batch']['GCell/s']} GCell/s")
+    if extra:
+        out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f0, coeffs)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

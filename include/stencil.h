@@ -113,12 +113,66 @@ STENCIL_API int stencil_run(stencil_plan_t plan, const float *in, float *out, in
 /*
  * Runs n independent grids, grid g with plans[g], ins[g], outs[g] and
  * steps[g] (host arrays of length n, device grid pointers), with the same
- * contract as n calls of stencil_run, enqueued on `stream` as one persistent
- * work-list launch per pass round.  The result of every grid is bitwise
- * equal to its own stencil_run.  Errors: EINVAL, ENOMEM, EDEVICE.
+ * result as n calls of stencil_run: every output is bitwise equal to its
+ * own stencil_run.  The call builds a batch (see stencil_batch_create, with
+ * default configuration) and launches it on `stream`; the batches of the
+ * last 4 distinct calls are kept, so a repeated call (same plans, pointers
+ * and steps) only replays its captured graph.  The grids run concurrently,
+ * so no grid may write memory another grid reads or writes (EINVAL), and a
+ * plan may appear only once.  n == 0 does nothing.  Errors: EINVAL, ENOMEM,
+ * EDEVICE, EUNSUPPORTED.
  */
 STENCIL_API int stencil_run_batched(int n, const stencil_plan_t *plans, const float *const *ins,
                         float *const *outs, const int64_t *steps, void *stream);
+
+/*
+ * The batched form as a reusable object.  Not in the paper, which runs one
+ * grid at a time; this is the many-grids form of the same method: grids are
+ * grouped into classes (dimension, radius, row alignment, size: 2D grids of
+ * >= 2^18 cells and 3D grids of >= 2^20 cells are "large"); each class has
+ * one kernel configuration and runs as a chain of pass rounds (K fused steps
+ * per round, a grid's last pass taking the remainder), each round one
+ * launch of a persistent work-list kernel whose workgroups take
+ * (grid, tile, segment) items from an atomic counter.  Class chains run
+ * concurrently on side streams.  The whole schedule is captured into one
+ * HIP graph at creation.
+ *
+ * stencil_batch_create: validates the grids as stencil_run_batched does and
+ * builds the batch; the pointers and steps are fixed for its lifetime.
+ *   tune  NULL, or a comma list of overrides: "2d.k=", "2d.ly=" (2D
+ *         classes), "3d.k=", "3d.wl=" (32|64), "3d.vec=" (4|8), "3d.nw=",
+ *         "3d.lz=" (3D classes) -- k is capped at the class's largest built
+ *         K, vec=8 applies only to aligned single-step R <= 2 classes with
+ *         wl=64 -- "streams=" (side streams, 1..16, default 4) and "graph="
+ *         (1 = replay the captured graph, the default; 0 = enqueue the
+ *         launches on every call).  Without overrides a class takes its
+ *         configuration from the tuning cache, else built-in defaults.
+ *   Grids with steps == 0, low-precision storage, or 3D planes of 2^31
+ *   bytes or more are run by their own plan inside the batch.
+ *   Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED.
+ * stencil_batch_launch: enqueues one run of every grid on `stream`.  A batch
+ *   must not run concurrently with itself (its counters and the plans'
+ *   scratch are shared).  Errors: EINVAL, EDEVICE.
+ * stencil_batch_autotune: times every feasible configuration of each class
+ *   on the batch's own grids (class chains run alone on `stream`), keeps
+ *   the fastest, records it in the tuning cache (STENCIL_TUNE_CACHE) and
+ *   re-captures the graph.  The outputs hold the batch's result afterwards.
+ *   report (NULL allowed): "<class> <config> <GCell/s>" lines.  Synchronises
+ *   the device.  Errors: EINVAL, EDEVICE.
+ * stencil_batch_describe: text summary (classes, configurations, rounds) into
+ *   buf (NULL allowed); returns the full length.
+ * stencil_batch_destroy: synchronises the device and frees the batch (not
+ *   its plans or grids).  NULL is ignored.
+ */
+typedef struct stencil_batch_s *stencil_batch_t; /* opaque, library-owned */
+STENCIL_API int stencil_batch_create(stencil_batch_t *batch, int n, const stencil_plan_t *plans,
+                         const float *const *ins, float *const *outs, const int64_t *steps,
+                         const char *tune);
+STENCIL_API int stencil_batch_launch(stencil_batch_t batch, void *stream);
+STENCIL_API int stencil_batch_autotune(stencil_batch_t batch, char *report, size_t report_len,
+                           void *stream);
+STENCIL_API int stencil_batch_describe(stencil_batch_t batch, char *buf, size_t len);
+STENCIL_API void stencil_batch_destroy(stencil_batch_t batch);
 
 /*
  * Measured autotuning (the empirical counterpart of the paper's model-guided

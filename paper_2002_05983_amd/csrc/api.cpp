@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cmath>
@@ -23,6 +24,7 @@ using namespace star;
 namespace {
 
 thread_local std::string g_last_error;
+std::atomic<uint64_t> g_plan_serial{0};
 
 int fail(int status, const char *fmt, ...) {
     char buf[512];
@@ -46,6 +48,21 @@ bool ranges_overlap(const void *a, const void *b, size_t bytes) {
 }  // namespace
 
 int star_set_error(int status, const char *msg) { return fail(status, "%s", msg); }
+void star_clear_error() { g_last_error.clear(); }
+
+int run_check(const stencil_plan_s *plan, const float *in, float *out, int64_t steps) {
+    if (!plan) return fail(STENCIL_EINVAL, "plan is NULL");
+    if (!in || !out) return fail(STENCIL_EINVAL, "in/out is NULL");
+    if (steps < 0) return fail(STENCIL_EINVAL, "steps must be >= 0 (got %lld)", (long long)steps);
+    if (((uintptr_t)in | (uintptr_t)out) & 3) return fail(STENCIL_EINVAL, "grids must be 4-byte aligned");
+    const size_t bytes = (size_t)plan->ncells * sizeof(float);
+    if (ranges_overlap(in, out, bytes)) return fail(STENCIL_EINVAL, "in and out overlap");
+    if (ranges_overlap(in, plan->scratch, bytes) || ranges_overlap(out, plan->scratch, bytes))
+        return fail(STENCIL_EINVAL, "in/out overlap the plan's scratch");
+    if (plan->storage != STENCIL_F32 && ((uintptr_t)out & 15))
+        return fail(STENCIL_EINVAL, "low-precision storage needs a 16-byte aligned out");
+    return STENCIL_OK;
+}
 
 extern "C" {
 
@@ -111,6 +128,7 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
     for (int k = 0; k < npts; ++k) p->cf.c[k] = coeffs[k];
     p->storage = storage;
     p->anchor_m = anchor_m;
+    p->serial = ++g_plan_serial;
     // the configuration is validated before any device call, so a bad
     // request reports EINVAL even where no device is present
     hipError_t e = hipGetDevice(&p->device);
@@ -197,31 +215,10 @@ int stencil_plan_describe(stencil_plan_t plan, char *buf, size_t len) {
 
 int stencil_run(stencil_plan_t plan, const float *in, float *out, int64_t steps, void *stream) {
     g_last_error.clear();
-    if (!plan) return fail(STENCIL_EINVAL, "plan is NULL");
-    if (!in || !out) return fail(STENCIL_EINVAL, "in/out is NULL");
-    if (steps < 0) return fail(STENCIL_EINVAL, "steps must be >= 0 (got %lld)", (long long)steps);
-    if (((uintptr_t)in | (uintptr_t)out) & 3) return fail(STENCIL_EINVAL, "grids must be 4-byte aligned");
-    const size_t bytes = (size_t)plan->ncells * sizeof(float);
-    if (ranges_overlap(in, out, bytes)) return fail(STENCIL_EINVAL, "in and out overlap");
-    if (ranges_overlap(in, plan->scratch, bytes) || ranges_overlap(out, plan->scratch, bytes))
-        return fail(STENCIL_EINVAL, "in/out overlap the plan's scratch");
-    if (plan->storage != STENCIL_F32 && ((uintptr_t)out & 15))
-        return fail(STENCIL_EINVAL, "low-precision storage needs a 16-byte aligned out");
+    const int rc = run_check(plan, in, out, steps);
+    if (rc != STENCIL_OK) return rc;
     const hipError_t e = plan_enqueue(plan, in, out, steps, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, steps == 0 ? "hipMemcpyAsync" : "kernel launch");
-    return STENCIL_OK;
-}
-
-int stencil_run_batched(int n, const stencil_plan_t *plans, const float *const *ins,
-                        float *const *outs, const int64_t *steps, void *stream) {
-    g_last_error.clear();
-    if (n < 0) return fail(STENCIL_EINVAL, "n must be >= 0");
-    if (n == 0) return STENCIL_OK;
-    if (!plans || !ins || !outs || !steps) return fail(STENCIL_EINVAL, "NULL batch array");
-    for (int g = 0; g < n; ++g) {
-        int rc = stencil_run(plans[g], ins[g], outs[g], steps[g], stream);
-        if (rc != STENCIL_OK) return rc;
-    }
     return STENCIL_OK;
 }
 

@@ -27,6 +27,7 @@ struct stencil_plan_s {
     int storage = 0;
     int anchor_m = 0;
     int device = 0;
+    uint64_t serial = 0;       // unique per plan created in this process
     float *scratch = nullptr;  // one FP32 grid, ping-pong partner of `out` (the anchor for F16/BF16)
     LowpState *lowp = nullptr; // low-precision state when storage != F32
 
@@ -51,6 +52,12 @@ hipError_t plan_enqueue(const stencil_plan_s *p, const float *in, float *out, in
                         hipStream_t stream);
 // Configuration recorded for this problem in the tuning cache, if any.
 bool tune_cache_lookup(const stencil_plan_s *p, std::string &config);
+// The tuning cache (file named by STENCIL_TUNE_CACHE): lines of
+// "<key>\t<config>\t<GCell/s>"; the last line of a key wins.
+bool tune_cache_get(const std::string &key, std::string &config);
+void tune_cache_put(const std::string &key, const std::string &config, double gcells);
+// Base architecture name of a device ("gfx950"), "unknown" if unavailable.
+std::string tune_arch_name(int device);
 // Splits `steps` into the K of each pass.
 void plan_pass_schedule(const stencil_plan_s *p, int64_t steps, std::vector<int> &passes);
 // Enqueues one pass of `k` fused steps from src to dst.
@@ -65,5 +72,9 @@ void lowp_release(stencil_plan_s *p);
 hipError_t lowp_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
                         hipStream_t stream);
 
+// Checks the arguments of one stencil_run (also used per grid of a batch).
+int run_check(const stencil_plan_s *plan, const float *in, float *out, int64_t steps);
+
 // Records a failure for stencil_last_error() and returns status.
 int star_set_error(int status, const char *msg);
+void star_clear_error();

@@ -1,0 +1,222 @@
+// star2d_body.hpp -- 2D star stencil, x-strip per wavefront, y streamed, K fused steps.
+//
+// The per-wavefront body shared by the single-grid kernel and the batched
+// work-list kernel.
+//
+// Method (Sec. III.A of the paper: 1.5D spatial blocking -- block x, stream
+// y -- combined with temporal blocking by a chain of K stages and
+// overlapped halos, Eq. (2)):
+//   * One wavefront owns a strip of 64 lanes x 4 cells = 256 columns: a
+//     TX-column output tile plus a halo of H = roundup(K*R, 4) columns per
+//     side.  Each lane holds 4 consecutive cells of a row; rows are read and
+//     written with one 128-bit access per lane.
+//   * The wavefront streams rows y0-K*R .. y1-1+K*R of its y-segment.  Stage
+//     s (1..K) applies one time step and runs R rows behind stage s-1, like
+//     the paper's PE chain.  Each stage keeps the last 2R+1 rows of its input
+//     in a register queue: the y-neighbours.  The x-neighbours of the
+//     queue's centre row come from the lane's own registers and, across the
+//     lane boundary, from the adjacent lanes through DPP wave shifts.  Only
+//     the K-th stage is written back, so one pass moves 8 bytes per cell for
+//     K steps.
+//   * Halo cells are recomputed by neighbouring strips instead of exchanged
+//     (overlapped blocking); the invalid region grows R columns per stage
+//     from each strip edge and never reaches the output tile.
+//   * Clamp boundary (Sec. III.B), applied to every stage's field: rows
+//     above the grid are filled with the stage's row 0 when it is produced,
+//     rows below take the stage's row ny-1, and columns outside [0, nx) are
+//     overwritten with the border column of the same stage and row.
+//   * Each cell is c_C*f_C followed by one FMA per neighbour in coefficient
+//     order (W, E, S, N for i = 1..R), the library-wide operation order.
+#pragma once
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace star {
+namespace s2d {
+
+constexpr int VEC = kVec2D;
+
+// Cells of one row of one stage.  q is a circular buffer of rows of the
+// stage's input (NS slots); CS is the slot of the centre row (compile-time).
+template <int R, int NS, int CS>
+__device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
+                                           float (&res)[VEC]) {
+    float left[R + 1], right[R + 1];
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);  // column base - k
+        right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);   // column base + VEC - 1 + k
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        float acc = cf.c[0] * q[CS][e];
+#pragma unroll
+        for (int i = 1; i <= R; ++i) {
+            const float w = (e - i >= 0) ? q[CS][e - i] : left[i - e];
+            const float ea = (e + i < VEC) ? q[CS][e + i] : right[e + i - VEC + 1];
+            const float s = q[(CS - i + NS) % NS][e];
+            const float n = q[(CS + i) % NS][e];
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], w, acc);
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], ea, acc);
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], s, acc);
+            acc = __builtin_fmaf(cf.c[coef_index<2>(kN, i)], n, acc);
+        }
+        res[e] = acc;
+    }
+}
+
+// One wavefront's work: strip `strip` (TX output columns) of y-segment `seg`
+// (ly output rows) of one grid.  Wave-level: no barriers, no LDS.  Every
+// argument is wave-uniform.
+template <int R, int K, int M, bool ALIGNED>
+__device__ __forceinline__ void star2d_body(const float *__restrict__ src, float *__restrict__ dst,
+                                            int nx, int ny, int ly, int strip, int seg,
+                                            const Coefs &cf) {
+    constexpr int P = 2 * R + 1;  // rows a stage keeps: its y-window
+    constexpr int NQ = M * P;     // input ring: y-window plus (M-1)*P rows in flight
+    constexpr int H = star2d_halo(K, R);
+    constexpr int TX = star2d_tile_x(K, R);
+    static_assert(R <= VEC, "x-neighbours must come from the adjacent lane");
+
+    const int lane = threadIdx.x & 63;
+    const int xs = strip * TX - H;  // first column held by lane 0
+    const int col0 = xs + lane * VEC;
+    const int y0 = seg * ly;
+    const int y1 = min(y0 + ly, ny);
+    const int jstart = y0 - K * R;
+    const int niter = (y1 - y0) + 2 * K * R;
+    const int jlast = jstart + niter - 1;
+    const bool left_edge = xs < 0;
+    const bool right_edge = xs + 64 * VEC > nx;
+    const int out_lo = max(xs + H, 0);
+    const int out_hi = min(xs + H + TX, nx);
+
+    // Clamp in x: cells left of column 0 take column 0, cells right of
+    // column nx-1 take column nx-1 (of the same row and stage).
+    auto xfix = [&](float (&v)[VEC]) STAR_INLINE {
+        if (left_edge) {
+            const int l0 = (-xs) / VEC;  // lane whose element 0 is column 0
+            const float b = lane_value(v[0], l0);
+            if (lane < l0) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[e] = b;
+            }
+        }
+        if (right_edge) {
+            const int off = nx - 1 - xs;
+            const int lr = off / VEC, er = off % VEC;
+            float t = v[0];
+#pragma unroll
+            for (int e = 1; e < VEC; ++e) t = (er == e) ? v[e] : t;
+            const float b = lane_value(t, lr);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = (col0 + e >= nx) ? b : v[e];
+        }
+    };
+
+    // Issues the load of input row j (clamped to the grid in y) into v.
+    // Rows past the segment's last one are never needed; they are re-read
+    // as the last row.  The x-clamp of a loaded row is applied when the row
+    // enters stage 1 (consume_row), so no load is waited for early.
+    auto load_row = [&](int j, float (&v)[VEC]) STAR_INLINE {
+        const float *row = src + (size_t)clampi(min(j, jlast), ny) * (size_t)nx;
+        if constexpr (ALIGNED) {
+            const int c = min(max(col0, 0), nx - VEC);
+            const float4 t = *reinterpret_cast<const float4 *>(row + c);
+            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = row[clampi(col0 + e, nx)];
+        }
+    };
+
+    // q0: ring of NQ input rows, loaded straight into their slots.
+    // q[s-1] (s = 2..K): last P rows of the stage-(s-1) field.
+    float q0[NQ][VEC];
+    float q[K > 1 ? K - 1 : 1][P][VEC];
+#pragma unroll
+    for (int s = 0; s < (K > 1 ? K - 1 : 1); ++s)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q[s][p][e] = 0.0f;
+#pragma unroll
+    for (int p = 0; p < NQ; ++p)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) q0[p][e] = 0.0f;
+
+    constexpr int DIST = NQ - P;  // prefetch distance in rows
+    static_for<0, DIST>([&](auto phc) STAR_INLINE {
+        constexpr int PH = decltype(phc)::value;
+        load_row(jstart + PH, q0[PH]);
+    });
+
+    // One streamed row: iteration n, ring slot PH = n mod NQ.
+    auto step_row = [&](auto phc, int n) STAR_INLINE {
+        constexpr int PH = decltype(phc)::value;
+        const int j = jstart + n;  // row entering stage 1
+        load_row(j + DIST, q0[(PH + DIST) % NQ]);
+        if constexpr (ALIGNED) xfix(q0[PH]);
+
+        static_for<1, K + 1>([&](auto sc) STAR_INLINE {
+            constexpr int S = decltype(sc)::value;
+            const int r = j - S * R;  // row produced by stage S
+            float res[VEC];
+            if constexpr (S == 1)
+                star2d_row<R, NQ, (PH - R + NQ) % NQ>(q0, cf, res);
+            else
+                star2d_row<R, P, (PH % P - R + P) % P>(q[S - 2], cf, res);
+            if constexpr (S < K) {
+                constexpr int W = PH % P;  // slot of this row in the stage's window
+                if (r >= ny) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(W + P - 1) % P][e];
+                } else {
+                    xfix(res);
+                }
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) q[S - 1][W][e] = res[e];
+                if (r == 0) {
+                    static_for<1, R + 1>([&](auto mc) STAR_INLINE {
+                        constexpr int MM = decltype(mc)::value;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) q[S - 1][(W - MM + P) % P][e] = res[e];
+                    });
+                }
+            } else {
+                // Stage K: write row r.  The store is issued on every row;
+                // rows of the wind-up and lanes outside the output tile get
+                // an out-of-range offset and write nothing.
+                const bool row_ok = r >= y0 && r < y1;
+                const auto rs = buffer_rsrc(dst + (size_t)clampi(r, ny) * (size_t)nx, nx * 4);
+                if constexpr (ALIGNED) {
+                    const bool ok = row_ok && col0 >= out_lo && col0 + VEC <= out_hi;
+                    buffer_store4(rs, ok ? col0 * 4 : kOutOfRange, res[0], res[1], res[2], res[3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int c = col0 + e;
+                        const bool ok = row_ok && c >= out_lo && c < out_hi;
+                        buffer_store1(rs, ok ? c * 4 : kOutOfRange, res[e]);
+                    }
+                }
+            }
+        });
+    };
+
+    int n0 = 0;
+    for (; n0 + NQ <= niter; n0 += NQ) {
+        static_for<0, NQ>([&](auto phc) STAR_INLINE { step_row(phc, n0 + decltype(phc)::value); });
+    }
+    static_for<0, NQ>([&](auto phc) STAR_INLINE {
+        if (n0 + decltype(phc)::value < niter) step_row(phc, n0 + decltype(phc)::value);
+    });
+}
+
+// Input-ring multiple: deeper prefetch for the memory-bound small-K passes.
+template <int R, int K>
+constexpr int ring_mult() { return K * R <= 2 ? 3 : 2; }
+
+}  // namespace s2d
+}  // namespace star

@@ -1,34 +1,7 @@
-// star3d.hip -- 3D star stencil: xy tile in LDS, z streamed, K fused steps.
+// star3d.hip -- single-grid launch of the 3D star stencil (method in star3d_body.hpp).
 //
 // Compiled once per radius with -DSTAR_R=<1..4>.
-//
-// Method (Sec. III.A of the paper: 2.5D spatial blocking -- block x and y,
-// stream z -- combined with temporal blocking by a chain of K stages and
-// overlapped halos, Eq. (2)):
-//   * A workgroup owns an xy tile: NW wavefronts of 64/WL tile rows each.
-//     WL lanes of a wavefront hold VEC consecutive cells each, so a row spans
-//     WL*VEC columns.  With WL = 64, a grid at most that wide is one tile and
-//     needs no x halo; otherwise tiles overlap by Hx = roundup(K*R, VEC)
-//     columns per side (the lanes at the ends of a row then hold halo cells,
-//     so a DPP shift that crosses from one row into the next only ever
-//     feeds halo cells).
-//   * Rows: the tile's TY output rows, (K-1)*R computed halo rows per side
-//     (stages 1..K-1 produce the values the next stage's halo needs), and R
-//     load-only rows per side that only supply stage 1's y-neighbours.
-//   * z is streamed.  Stage s (1..K) runs R planes behind stage s-1; each
-//     stage keeps the last 2R+1 planes of its input column in registers (the
-//     z-neighbours).  Per plane, every stage writes its centre plane row to
-//     LDS (double-buffered), one barrier, then reads its y-neighbours from
-//     LDS, its x-neighbours from its own and adjacent lanes (DPP wave
-//     shifts), and applies one step.  Only stage K is written back.
-//   * Clamp boundary (Sec. III.B) at every stage: y-neighbour rows are
-//     clamped to the grid when read from LDS; z planes before the grid are
-//     filled with a stage's plane 0 when it is produced, planes after it
-//     repeat plane nz-1; columns outside [0, nx) take the border column.
-//   * Each cell is c_C*f_C followed by one FMA per neighbour in coefficient
-//     order (W, E, S, N, B, A for i = 1..R), the library-wide order.
-#include "common.hpp"
-#include "launch.hpp"
+#include "star3d_body.hpp"
 
 #ifndef STAR_R
 #error "compile with -DSTAR_R=<radius>"
@@ -38,278 +11,17 @@ namespace star {
 
 namespace {
 
-// LDS row layout: chunk-major, [VEC/4][WL lanes][4 floats], so that every
-// 128-bit LDS access of a row's lanes covers consecutive addresses.
-template <int VEC, int WL>
-__device__ __forceinline__ int lds_off(int lr, int chunk) {
-    return (chunk * WL + lr) * 4;
-}
-
-template <int VEC, int WL>
-__device__ __forceinline__ void lds_write_row(float *row, int lr, const float (&v)[VEC]) {
-#pragma unroll
-    for (int c = 0; c < VEC / 4; ++c)
-        *reinterpret_cast<float4 *>(row + lds_off<VEC, WL>(lr, c)) =
-            make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
-}
-
-template <int VEC, int WL>
-__device__ __forceinline__ void lds_read_row(const float *row, int lr, float (&v)[VEC]) {
-#pragma unroll
-    for (int c = 0; c < VEC / 4; ++c) {
-        const float4 t = *reinterpret_cast<const float4 *>(row + lds_off<VEC, WL>(lr, c));
-        v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
-    }
-}
+using s3d::prefetch3;
+using s3d::star3d_body;
 
 template <int R, int K, int VEC, int WL, int D, bool ALIGNED>
 __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ src,
                                                       float *__restrict__ dst, int nx, int ny,
                                                       int nz, int hx, int tx, int ntx, int nty,
                                                       int lz, Coefs cf) {
-    constexpr int P = 2 * R + 1;      // planes a stage keeps: its z-window
-    constexpr int NQ = P + D;         // input ring: window plus D planes in flight
-    constexpr int DIST = D;           // prefetch distance in planes
-    // Unrolled planes per loop trip: every ring index must be compile-time,
-    // so the trip covers a whole number of turns of each ring.
-    constexpr int U = (K == 1) ? NQ : NQ * P / gcd_i(NQ, P);
-    constexpr int RPW = 64 / WL;      // tile rows per wavefront
-    constexpr int W = WL * VEC;       // columns per tile row
-    constexpr int ROWF = W;           // floats per LDS row
-    static_assert(R <= VEC && VEC % 4 == 0 && 64 % WL == 0, "bad vector width");
-    extern __shared__ float lds[];    // [K][2][NT][ROWF]
-
-    const int lane = threadIdx.x & 63;
-    const int lr = lane % WL;         // lane within its tile row
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nt = (blockDim.x >> 6) * RPW;  // tile rows
-    const int ty = nt - 2 * K * R;    // output rows of the tile
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int strip = lb % ntx;
-    const int ytile = (lb / ntx) % nty;
-    const int zseg = lb / (ntx * nty);
-    const int ty0 = ytile * ty;
-    const int trow = w * RPW + lane / WL;  // this lane's tile row
-    const int y = ty0 - K * R + trow;      // and grid row
-    const int yc = clampi(y, ny);
-    // rows 0..R-1 and nt-R..nt-1 only feed stage 1; a wavefront made of
-    // such rows only loads
-    const bool load_only = (w * RPW + RPW - 1 < R) || (w * RPW >= nt - R);
-    const int xs = strip * tx - hx;   // first column held by lane 0 of a row
-    const int col0 = xs + lr * VEC;
-    const int z0 = zseg * lz;
-    const int z1 = min(z0 + lz, nz);
-    const int zstart = z0 - K * R;
-    const int niter = (z1 - z0) + 2 * K * R;
-    const int zlast = zstart + niter - 1;
-    const bool left_edge = xs < 0;
-    const bool right_edge = xs + W > nx;
-    const int out_lo = max(xs + hx, 0);
-    const int out_hi = min(xs + hx + tx, nx);
-    const bool row_out = y >= ty0 && y < ty0 + ty && y < ny;
-    const size_t plane = (size_t)nx * (size_t)ny;
-    const int plane_bytes = (int)(plane * sizeof(float));  // < 2^31, checked by the launcher
-
-    // LDS row of stage s (0-based), buffer b, tile row r.
-    auto lds_row = [&](int s, int b, int r) STAR_INLINE -> float * {
-        return lds + ((size_t)((s * 2 + b) * nt + r)) * ROWF;
-    };
-    // Tile row holding grid row clamp(yy) (clamped into the tile as well).
-    auto tile_row = [&](int yy) STAR_INLINE -> int {
-        const int r = clampi(yy, ny) - (ty0 - K * R);
-        return r < 0 ? 0 : (r >= nt ? nt - 1 : r);
-    };
-    // Value of v in lane `l` of this lane's tile row.
-    auto row_value = [&](float v, int l) STAR_INLINE -> float {
-        float b = lane_value(v, l);
-#pragma unroll
-        for (int k = 1; k < RPW; ++k) b = (lane / WL == k) ? lane_value(v, k * WL + l) : b;
-        return b;
-    };
-
-    auto xfix = [&](float (&v)[VEC]) STAR_INLINE {
-        if (left_edge) {
-            const int l0 = (-xs) / VEC;
-            const float b = row_value(v[0], l0);
-            if (lr < l0) {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) v[e] = b;
-            }
-        }
-        if (right_edge) {
-            const int off = nx - 1 - xs;
-            const int lrr = off / VEC, er = off % VEC;
-            float t = v[0];
-#pragma unroll
-            for (int e = 1; e < VEC; ++e) t = (er == e) ? v[e] : t;
-            const float b = row_value(t, lrr);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) v[e] = (col0 + e >= nx) ? b : v[e];
-        }
-    };
-
-    auto load_plane = [&](int zz, float (&v)[VEC]) STAR_INLINE {
-        const float *row = src + (size_t)clampi(min(zz, zlast), nz) * plane + (size_t)yc * nx;
-        if constexpr (ALIGNED) {
-#pragma unroll
-            for (int c = 0; c < VEC / 4; ++c) {
-                const int cc = min(max(col0 + 4 * c, 0), nx - 4);
-                const float4 t = *reinterpret_cast<const float4 *>(row + cc);
-                v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) v[e] = row[clampi(col0 + e, nx)];
-        }
-    };
-
-    // Cells of one stage: centre row ctr, queue q (z-window, NS slots, centre
-    // slot CS), LDS buffer of the centre plane for y-neighbours.
-    auto cells = [&](auto nsc, auto csc, const float (&q)[decltype(nsc)::value][VEC], int s,
-                     int b, float (&res)[VEC]) STAR_INLINE {
-        constexpr int NS = decltype(nsc)::value;
-        constexpr int CS = decltype(csc)::value;
-        float left[R + 1], right[R + 1];
-#pragma unroll
-        for (int k = 1; k <= R; ++k) {
-            left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);
-            right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);
-        }
-        float acc[VEC];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = cf.c[0] * q[CS][e];
-#pragma unroll
-        for (int i = 1; i <= R; ++i) {
-            // keep the scheduler from hoisting every distance's LDS reads at
-            // once (register pressure at large R)
-            if (i > 1) __builtin_amdgcn_sched_barrier(0);
-            float sv[VEC], nv[VEC];
-            lds_read_row<VEC, WL>(lds_row(s, b, tile_row(y - i)), lr, sv);
-            lds_read_row<VEC, WL>(lds_row(s, b, tile_row(y + i)), lr, nv);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const float wv = (e - i >= 0) ? q[CS][e - i] : left[i - e];
-                const float ev = (e + i < VEC) ? q[CS][e + i] : right[e + i - VEC + 1];
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kW, i)], wv, acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kE, i)], ev, acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kS, i)], sv[e], acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kN, i)], nv[e], acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kB, i)], q[(CS - i + NS) % NS][e], acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kA, i)], q[(CS + i) % NS][e], acc[e]);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) res[e] = acc[e];
-    };
-
-    float q0[NQ][VEC];
-    float q[K > 1 ? K - 1 : 1][P][VEC];
-#pragma unroll
-    for (int s = 0; s < (K > 1 ? K - 1 : 1); ++s)
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) q[s][p][e] = 0.0f;
-#pragma unroll
-    for (int p = 0; p < NQ; ++p)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) q0[p][e] = 0.0f;
-
-    static_for<0, DIST>([&](auto phc) STAR_INLINE {
-        load_plane(zstart + decltype(phc)::value, q0[decltype(phc)::value]);
-    });
-
-    auto step_plane = [&](auto phc, int n) STAR_INLINE {
-        constexpr int PH = decltype(phc)::value % NQ;  // slot in the input ring
-        constexpr int PS = decltype(phc)::value % P;   // slot in the stage windows
-        const int zl = zstart + n;  // plane entering stage 1
-        const int b = n & 1;        // LDS buffer of this iteration
-        load_plane(zl + DIST, q0[(PH + DIST) % NQ]);
-        if constexpr (ALIGNED) xfix(q0[PH]);
-        // centre planes of every stage into LDS
-        lds_write_row<VEC, WL>(lds_row(0, b, trow), lr, q0[(PH - R + NQ) % NQ]);
-        if (!load_only) {
-            static_for<2, K + 1>([&](auto sc) STAR_INLINE {
-                constexpr int S = decltype(sc)::value;
-                lds_write_row<VEC, WL>(lds_row(S - 1, b, trow), lr, q[S - 2][(PS - R + P) % P]);
-            });
-        }
-        __syncthreads();
-        if (!load_only) {
-            static_for<1, K + 1>([&](auto sc) STAR_INLINE {
-                constexpr int S = decltype(sc)::value;
-                const int r = zl - S * R;  // plane produced by stage S
-                float res[VEC];
-                if constexpr (S == 1)
-                    cells(std::integral_constant<int, NQ>{},
-                          std::integral_constant<int, (PH - R + NQ) % NQ>{}, q0, 0, b, res);
-                else
-                    cells(std::integral_constant<int, P>{},
-                          std::integral_constant<int, (PS - R + P) % P>{}, q[S - 2], S - 1, b,
-                          res);
-                if constexpr (S < K) {
-                    constexpr int WS = PS;
-                    if (r >= nz) {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(WS + P - 1) % P][e];
-                    } else {
-                        xfix(res);
-                    }
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) q[S - 1][WS][e] = res[e];
-                    if (r == 0) {
-                        static_for<1, R + 1>([&](auto mc) STAR_INLINE {
-                            constexpr int MM = decltype(mc)::value;
-#pragma unroll
-                            for (int e = 0; e < VEC; ++e) q[S - 1][(WS - MM + P) % P][e] = res[e];
-                        });
-                    }
-                } else {
-                    // one descriptor per plane (wave-uniform); the row goes
-                    // into the per-lane offset
-                    const bool ok_row = row_out && r >= z0 && r < z1;
-                    const auto rs = buffer_rsrc(dst + (size_t)clampi(r, nz) * plane, plane_bytes);
-                    const int rowoff = yc * nx;
-                    if constexpr (ALIGNED) {
-#pragma unroll
-                        for (int c = 0; c < VEC / 4; ++c) {
-                            const int cc = col0 + 4 * c;
-                            const bool ok = ok_row && cc >= out_lo && cc + 4 <= out_hi;
-                            buffer_store4(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[4 * c],
-                                          res[4 * c + 1], res[4 * c + 2], res[4 * c + 3]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            const int cc = col0 + e;
-                            const bool ok = ok_row && cc >= out_lo && cc < out_hi;
-                            buffer_store1(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[e]);
-                        }
-                    }
-                }
-            });
-        }
-    };
-
-    int n0 = 0;
-    for (; n0 + U <= niter; n0 += U) {
-        static_for<0, U>([&](auto phc) STAR_INLINE { step_plane(phc, n0 + decltype(phc)::value); });
-    }
-    static_for<0, U>([&](auto phc) STAR_INLINE {
-        if (n0 + decltype(phc)::value < niter) step_plane(phc, n0 + decltype(phc)::value);
-    });
-}
-
-// Prefetch depth (planes) per configuration, sized so that a 1024-thread
-// workgroup stays within 128 VGPRs per lane: deep for K = 1 (memory bound),
-// one window (D = P) for K > 1 so the unroll stays 2P.
-template <int K, int VEC, int WL>
-constexpr int prefetch3() {
-    constexpr int P = 2 * STAR_R + 1;
-    if constexpr (K > 1) return P;
-    if constexpr (VEC == 4 && WL == 32) return P + 3 > 12 ? 3 : 12 - P;  // two rows per wave
-    if constexpr (VEC == 4) return P + 4 > 12 ? 4 : 12 - P;  // ring of max(12, P + 4) planes
-    return 8 - P > 2 ? 8 - P : 2;                            // ring of max(8, P + 2) planes
+    star3d_body<R, K, VEC, WL, D, ALIGNED>(src, dst, nx, ny, nz, hx, tx, lb % ntx,
+                                           (lb / ntx) % nty, lb / (ntx * nty), lz, cf);
 }
 
 template <int K, int VEC, int WL, bool AL>
@@ -333,7 +45,7 @@ hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
     if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const size_t lds = (size_t)K * 2 * nt * W * sizeof(float);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    auto kern = star3d_stream<R, K, VEC, WL, prefetch3<K, VEC, WL>(), AL>;
+    auto kern = star3d_stream<R, K, VEC, WL, prefetch3<STAR_R, K, VEC, WL>(), AL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

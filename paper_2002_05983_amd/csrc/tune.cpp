@@ -26,16 +26,10 @@ std::mutex g_cache_mu;
 
 std::string cache_key(const stencil_plan_s *p) {
     char buf[160];
-    hipDeviceProp_t prop;
-    const char *arch = "unknown";
-    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
     snprintf(buf, sizeof buf, "ndim=%d R=%d storage=%d dims=%lldx%lldx%lld arch=%s", p->ndim,
-             p->radius, p->storage, (long long)p->nx, (long long)p->ny, (long long)p->nz, arch);
-    // keep only the architecture's base name (drop feature suffixes)
-    std::string k(buf);
-    const size_t colon = k.find(':', k.find("arch="));
-    if (colon != std::string::npos) k.resize(colon);
-    return k;
+             p->radius, p->storage, (long long)p->nx, (long long)p->ny, (long long)p->nz,
+             tune_arch_name(p->device).c_str());
+    return buf;
 }
 
 // Every configuration worth timing for this problem.
@@ -71,13 +65,22 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
 
 }  // namespace
 
-bool tune_cache_lookup(const stencil_plan_s *p, std::string &config) {
+std::string tune_arch_name(int device) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (device >= 0 && hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    // keep only the architecture's base name (drop feature suffixes)
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch;
+}
+
+bool tune_cache_get(const std::string &key, std::string &config) {
     const char *path = getenv("STENCIL_TUNE_CACHE");
     if (!path || !*path) return false;
     std::lock_guard<std::mutex> lk(g_cache_mu);
     FILE *f = fopen(path, "r");
     if (!f) return false;
-    const std::string key = cache_key(p);
     char line[512];
     bool found = false;
     while (fgets(line, sizeof line, f)) {
@@ -93,14 +96,18 @@ bool tune_cache_lookup(const stencil_plan_s *p, std::string &config) {
     return found;
 }
 
-static void tune_cache_store(const stencil_plan_s *p, const std::string &config, double gcells) {
+void tune_cache_put(const std::string &key, const std::string &config, double gcells) {
     const char *path = getenv("STENCIL_TUNE_CACHE");
     if (!path || !*path) return;
     std::lock_guard<std::mutex> lk(g_cache_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s\t%s\t%.2f\n", cache_key(p).c_str(), config.c_str(), gcells);
+    fprintf(f, "%s\t%s\t%.2f\n", key.c_str(), config.c_str(), gcells);
     fclose(f);
+}
+
+bool tune_cache_lookup(const stencil_plan_s *p, std::string &config) {
+    return tune_cache_get(cache_key(p), config);
 }
 
 extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float *out, char *report,
@@ -160,7 +167,7 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float
         return star_set_error(STENCIL_EDEVICE, "best configuration did not re-apply");
     }
     plan->tuned_by = "autotune";
-    tune_cache_store(plan, results[0].config, results[0].gcells);
+    tune_cache_put(cache_key(plan), results[0].config, results[0].gcells);
     if (report && report_len > 0) {
         std::string r;
         for (const Result &x : results) {

@@ -33,6 +33,13 @@ SIGNATURES = {
     "stencil_run": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "stencil_run_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), _i64p, _vp]),
+    "stencil_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64p,
+                                            ctypes.c_char_p]),
+    "stencil_batch_launch": (ctypes.c_int, [_vp, _vp]),
+    "stencil_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t, _vp]),
+    "stencil_batch_describe": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "stencil_batch_destroy": (None, [_vp]),
     "stencil_plan_query": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_double)]),
@@ -177,13 +184,14 @@ class Plan:
             pass
 
 
-def run_batched(plans, ins, outs, steps, stream=None):
-    """One batched launch over independent grids (see stencil_run_batched)."""
+def _batch_arrays(plans, ins, outs, steps):
     n = len(plans)
     if not (len(ins) == len(outs) == n):
         raise ValueError("plans, ins and outs must have the same length")
     if isinstance(steps, int):
         steps = [steps] * n
+    if len(steps) != n:
+        raise ValueError("steps must be an int or have one entry per grid")
     for p, i, o in zip(plans, ins, outs):
         _check_grid(i, p.ncells, "in")
         _check_grid(o, p.ncells, "out")
@@ -191,7 +199,54 @@ def run_batched(plans, ins, outs, steps, stream=None):
     ip = (_vp * n)(*[t.data_ptr() for t in ins])
     op = (_vp * n)(*[t.data_ptr() for t in outs])
     st = (ctypes.c_int64 * n)(*[int(s) for s in steps])
+    return n, hp, ip, op, st
+
+
+def run_batched(plans, ins, outs, steps, stream=None):
+    """Runs independent grids as one batch (see stencil_run_batched)."""
+    n, hp, ip, op, st = _batch_arrays(plans, ins, outs, steps)
     _check(load().stencil_run_batched(n, hp, ip, op, st, _stream_ptr(stream)))
+
+
+class Batch:
+    """A reusable batch of grids (stencil_batch_create/launch/destroy).
+
+    The plans and tensors must stay alive, and in place, while the batch
+    exists; the batch keeps references to them.
+    """
+
+    def __init__(self, plans, ins, outs, steps, tune=None):
+        n, hp, ip, op, st = _batch_arrays(plans, ins, outs, steps)
+        self._keep = (list(plans), list(ins), list(outs))
+        h = _vp()
+        _check(load().stencil_batch_create(ctypes.byref(h), n, hp, ip, op, st,
+                                           tune.encode() if tune else None))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().stencil_batch_launch(self._h, _stream_ptr(stream)))
+
+    def autotune(self, stream=None) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(load().stencil_batch_autotune(self._h, buf, len(buf), _stream_ptr(stream)))
+        return buf.value.decode()
+
+    def describe(self) -> str:
+        n = load().stencil_batch_describe(self._h, None, 0)
+        buf = ctypes.create_string_buffer(max(1, n + 1))
+        load().stencil_batch_describe(self._h, buf, len(buf))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().stencil_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def reduce_f64(x, ref=None, stream=None):

@@ -89,7 +89,8 @@ def sinusoid_grid(seed: int, n: int, modes: int = 8, noise: float = 1e-3,
     f(x,y,z) = sum_j a_j sin(2 pi (kx_j x + ky_j y + kz_j z) / n + phi_j)
                + noise * U[0,1)
     with a_j ~ U[0.5,1), integer k per axis in [0, kmax] (not all zero) and
-    phi_j ~ U[0, 2 pi).  Evaluated in FP64 plane by plane, rounded to FP32.
+    phi_j ~ U[0, 2 pi).  Evaluated in FP64 (each mode split by the angle
+    addition formula into an xy factor and a z factor), rounded to FP32.
     """
     draws = uniform01_f64(seed, 16 * modes)
     amp, kvec, phase = [], [], []
@@ -105,15 +106,28 @@ def sinusoid_grid(seed: int, n: int, modes: int = 8, noise: float = 1e-3,
                 k = [1, 0, 0]
         kvec.append(k)
         phase.append(2.0 * math.pi * d[15])
-    out = np.empty((n, n, n), dtype=np.float32)
+    # sin(t_xy + t_z) = sin(t_xy) cos(t_z) + cos(t_xy) sin(t_z): the field is
+    # a (planes x 2*modes) by (2*modes x cells-per-plane) matrix product.
     ax = np.arange(n, dtype=np.float64)
     yy, xx = np.meshgrid(ax, ax, indexing="ij")
-    for z in range(n):
-        plane = np.zeros((n, n), dtype=np.float64)
-        for a, k, ph in zip(amp, kvec, phase):
-            plane += a * np.sin(2.0 * math.pi * (k[0] * xx + k[1] * yy + k[2] * z) / n + ph)
-        noise_vals = uniform01_f32(seed + 1, n * n, start=z * n * n).astype(np.float64)
-        out[z] = (plane + noise * noise_vals.reshape(n, n)).astype(np.float32)
+    basis = np.empty((2 * modes, n * n), dtype=np.float64)
+    for j, (k, ph) in enumerate(zip(kvec, phase)):
+        t_xy = (2.0 * math.pi * (k[0] * xx + k[1] * yy) / n + ph).ravel()
+        basis[2 * j] = np.sin(t_xy)
+        basis[2 * j + 1] = np.cos(t_xy)
+    out = np.empty((n, n, n), dtype=np.float32)
+    zc = max(1, (1 << 22) // (n * n))  # planes per chunk
+    for z0 in range(0, n, zc):
+        z = np.arange(z0, min(n, z0 + zc), dtype=np.float64)
+        w = np.empty((z.size, 2 * modes), dtype=np.float64)
+        for j, (a, k) in enumerate(zip(amp, kvec)):
+            t_z = 2.0 * math.pi * k[2] * z / n
+            w[:, 2 * j] = a * np.cos(t_z)
+            w[:, 2 * j + 1] = a * np.sin(t_z)
+        vals = w @ basis
+        noise_vals = uniform01_f32(seed + 1, z.size * n * n, start=z0 * n * n).astype(np.float64)
+        out[z0:z0 + z.size] = (vals + noise * noise_vals.reshape(z.size, n * n)).reshape(
+            z.size, n, n).astype(np.float32)
     return out
 
 

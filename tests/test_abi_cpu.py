@@ -27,6 +27,7 @@ def lib():
 def test_header_declares_the_abi():
     names = declared_functions()
     for must in ("stencil_plan", "stencil_plan_ex", "stencil_run", "stencil_run_batched",
+                 "stencil_batch_create", "stencil_batch_launch", "stencil_batch_autotune",
                  "stencil_plan_query", "stencil_reduce_f64", "stencil_plan_destroy",
                  "stencil_status_string", "stencil_last_error"):
         assert must in names
@@ -100,6 +101,24 @@ def test_run_and_reduce_reject_null(lib):
     assert lib.stencil_run_batched(-1, None, None, None, None, None) == -1
     assert lib.stencil_run_batched(0, None, None, None, None, None) == 0
     lib.stencil_plan_destroy(None)
+
+
+def test_batch_entry_points_reject_null(lib):
+    h = ctypes.c_void_p()
+    assert lib.stencil_batch_create(None, 1, None, None, None, None, None) == -1
+    assert lib.stencil_batch_create(ctypes.byref(h), 0, None, None, None, None, None) == -1
+    assert not h.value
+    assert lib.stencil_batch_create(ctypes.byref(h), 2, None, None, None, None, None) == -1
+    assert b"NULL" in lib.stencil_last_error()
+    plans = (ctypes.c_void_p * 1)(None)
+    ptrs = (ctypes.c_void_p * 1)(None)
+    steps = (ctypes.c_int64 * 1)(1)
+    assert lib.stencil_batch_create(ctypes.byref(h), 1, plans, ptrs, ptrs, steps, None) == -1
+    assert lib.stencil_run_batched(1, plans, ptrs, ptrs, steps, None) == -1
+    assert lib.stencil_batch_launch(None, None) == -1
+    assert lib.stencil_batch_autotune(None, None, 0, None) == -1
+    assert lib.stencil_batch_describe(None, None, 0) == -1
+    lib.stencil_batch_destroy(None)
 
 
 @pytest.mark.parametrize("ndim,dims,radius,tune,ok", [

@@ -251,3 +251,39 @@ def test_precision_form_error_and_speed_report(torch, st, oracle_mod):
         err = oracle_mod.rel_linf(y.cpu().numpy(), ref)
         assert err <= tol, (storage, m, err)
         plan.close()
+
+
+def _precision_reference():
+    from conftest import golden
+    import os
+    from conftest import ROOT
+    maxabs = None
+    with open(os.path.join(ROOT, "tests", "golden", "precision_128cube_r4_1000.txt")) as fh:
+        for line in fh:
+            if line.startswith("# maxabs"):
+                maxabs = float(line.split()[2])
+    rows = golden("precision_128cube_r4_1000.txt")
+    cells = [(int(r[0]), int(r[1]), int(r[2])) for r in rows]
+    vals = np.array([float(r[3]) for r in rows])
+    return maxabs, cells, vals
+
+
+@pytest.mark.parametrize("storage,m,tol", [("f32", 0, TOL_F64), ("f16", 10, 1e-3), ("f16", 50, 1e-3),
+                                           ("bf16", 10, 1e-2), ("bf16", 50, 1e-2)])
+def test_precision_workload_128cube_vs_stored_fp64(torch, st, storage, m, tol):
+    """1000 steps of radius 4 on the 128^3 sinusoid grid against the FP64
+    oracle values stored for sampled cells (corners included)."""
+    maxabs, cells, want = _precision_reference()
+    n = 128
+    f = synth.sinusoid_grid(4, n)
+    c = synth.coefficients(3004, 3, 4)
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    plan = st.Plan((n, n, n), 4, c, storage=storage, anchor_m=m)
+    plan.run(x, y, 1000)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    vals = np.array([got[z, yy, xx] for xx, yy, z in cells], dtype=np.float64)
+    err = np.max(np.abs(vals - want)) / maxabs
+    assert err <= tol, (storage, m, err)
+    plan.close()
