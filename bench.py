@@ -185,7 +185,7 @@ def bench_precision(stencil, synth, torch, dev, side=768, time_steps=1000, radiu
              "config": p32.describe()}]
     ref64 = ref.double()
     y = torch.empty_like(x)
-    for storage in ("f16", "bf16"):
+    for storage in ("f16", "bf16", "f16-scaled", "bf16-scaled"):
         for m in anchors:
             p = stencil.Plan(shape, radius, c, storage=storage, anchor_m=m)
             ms = timed(p, y)
@@ -204,7 +204,8 @@ def bench_precision(stencil, synth, torch, dev, side=768, time_steps=1000, radiu
     idx = torch.tensor([(z * n + yy) * n + xx for xx, yy, z in pts], device=dev)
     wantt = torch.tensor(want, dtype=torch.float64, device=dev)
     fp64 = {}
-    for storage, m in [("f32", 0)] + [(s_, m_) for s_ in ("f16", "bf16") for m_ in anchors]:
+    for storage, m in [("f32", 0)] + [(s_, m_) for s_ in ("f16", "bf16", "f16-scaled", "bf16-scaled")
+                                      for m_ in anchors]:
         p = stencil.Plan((n, n, n), radius, c, storage=storage, anchor_m=m)
         p.run(xs, ys, time_steps, stream=stream)
         got = ys.view(-1)[idx].double()
@@ -217,7 +218,9 @@ def bench_precision(stencil, synth, torch, dev, side=768, time_steps=1000, radiu
     p32.close()
     return {"workload": f"precision form: 3D star r={radius} on {side}^3 seeded sinusoid grid "
                         f"(8 modes + 1e-3 noise), {time_steps} steps, FP32 vs FP16/BF16 storage "
-                        f"with per-64^3-tile power-of-two scales, FP32 re-anchor every m steps",
+                        f"with per-64^3-tile power-of-two scales and FP32 arithmetic, re-anchored "
+                        f"every m steps: anchored delta (f16, bf16) and scaled state "
+                        f"(f16-scaled, bf16-scaled)",
             "fp64_error_workload": f"{n}^3, same recipe, {time_steps} steps, FP64 oracle on "
                                    f"{len(pts)} stored cells (8 corners + 248 drawn)",
             "rows": rows}

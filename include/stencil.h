@@ -62,9 +62,11 @@ enum stencil_boundary {
 };
 
 enum stencil_storage {
-    STENCIL_F32 = 0,  /* state kept in FP32 between passes               */
-    STENCIL_F16 = 1,  /* state kept in FP16 with per-tile 2^e scales     */
-    STENCIL_BF16 = 2  /* state kept in BF16 with per-tile 2^e scales     */
+    STENCIL_F32 = 0,         /* state kept in FP32 between passes                    */
+    STENCIL_F16 = 1,         /* FP32 anchor + FP16 delta with per-tile 2^e scales    */
+    STENCIL_BF16 = 2,        /* FP32 anchor + BF16 delta with per-tile 2^e scales    */
+    STENCIL_F16_SCALED = 3,  /* state itself in FP16 with per-tile 2^e scales        */
+    STENCIL_BF16_SCALED = 4  /* state itself in BF16 with per-tile 2^e scales        */
 };
 
 /*
@@ -87,9 +89,22 @@ STENCIL_API int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims
 
 /*
  * As stencil_plan, with extra controls:
- *   storage  STENCIL_F32, STENCIL_F16 or STENCIL_BF16 (state between passes).
- *   anchor_m for F16/BF16: the state is re-anchored in FP32 every anchor_m
- *            steps (>= 1); ignored for F32.
+ *   storage  STENCIL_F32, or one of the two low-precision forms (3D grids
+ *            with nx % 4 == 0; not in the paper, which computes in FP32 only,
+ *            Sec. IV.C).  Both store 16-bit codes q with one power-of-two
+ *            scale per 64^3 tile (value = q * 2^e, e = ceil(log2 B) - 14 for
+ *            a bound B on the tile's magnitude), compute every step in FP32
+ *            and return FP32.
+ *            STENCIL_F16 / STENCIL_BF16, anchored delta: an FP32 anchor A is
+ *            fixed per window of anchor_m steps and only the delta D = F - A
+ *            is stored; since one step S is linear, D evolves as
+ *            D <- S D + G with G = S A - A computed once per window in FP32;
+ *            A <- A + D at the window's end.
+ *            STENCIL_F16_SCALED / STENCIL_BF16_SCALED, scaled state: the state
+ *            itself is stored as codes between FP32 anchor steps (one FP32
+ *            step every anchor_m steps re-derives the scales).
+ *   anchor_m for the low-precision forms: steps per window (>= 1); ignored
+ *            for F32.
  *   tune     NULL for automatic selection, or a configuration string such as
  *            "naive", "k=4,ly=256" (2D) or "k=2,tx=120,ty=24,lz=64" (3D);
  *            unknown keys or infeasible values give EINVAL.

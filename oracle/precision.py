@@ -19,6 +19,17 @@ order):
     A = fl32(A + dec(D))
   result = A
 
+The scaled-state form (a second reading of the same storage) keeps the
+state itself as codes between FP32 anchor steps:
+
+  For each window of m steps (the last may be shorter):
+    eQ = tile exponents of max|A| per tile;  Q = encode(A, eQ)
+    repeat (window - 1) times:
+      e   = tile exponents of  s1 * max_{27 neighbour tiles} max|dec Q|
+      Q   = encode(fl32(S dec(Q)), e)
+    A = fl32(S dec(Q))                       one FP32 step (the anchor)
+  result = A
+
 Codes: value = q * 2^e.  Encoding scales by 2^-e (exact) and rounds to the
 nearest code, ties to even (IEEE binary16 via numpy, bfloat16 by the same
 rule on the top 16 bits of the binary32 pattern).  Tile exponent for a
@@ -141,5 +152,32 @@ def run(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
             e_d = e_new
             ddec = decode(d, per_cell(e_d, shape), codec)
         A = (A + ddec).astype(np.float32)
+        t += w
+    return A
+
+
+def run_scaled(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
+               threads: int = 0) -> np.ndarray:
+    """The scaled-state form on a 3D FP32 grid; returns the FP32 result."""
+    c32 = np.asarray(coeffs, dtype=np.float32)
+    s1 = 0.0
+    for v in c32:  # summed in coefficient order, in double
+        s1 += abs(float(v))
+    A = np.array(f0, dtype=np.float32, copy=True)
+    shape = A.shape
+
+    def step(x):
+        return oracle.star_run_f32(x, c32, radius, 1, threads)
+
+    t = 0
+    while t < steps:
+        w = min(m, steps - t)
+        e = exponents(tile_max(A))
+        qdec = decode(encode(A, per_cell(e, shape), codec), per_cell(e, shape), codec)
+        for _ in range(1, w):
+            bound = s1 * neighbour_max(tile_max(qdec)).astype(np.float64)
+            e = exponents(bound)
+            qdec = decode(encode(step(qdec), per_cell(e, shape), codec), per_cell(e, shape), codec)
+        A = step(qdec)
         t += w
     return A

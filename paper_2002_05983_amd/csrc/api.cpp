@@ -97,7 +97,7 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
         return fail(STENCIL_EINVAL, "ncoeffs must be 1+2*ndim*radius = %d (got %d)", npts, ncoeffs);
     if (boundary != STENCIL_BOUNDARY_CLAMP)
         return fail(STENCIL_EINVAL, "unsupported boundary %d (only clamp)", boundary);
-    if (storage != STENCIL_F32 && storage != STENCIL_F16 && storage != STENCIL_BF16)
+    if (storage < STENCIL_F32 || storage > STENCIL_BF16_SCALED)
         return fail(STENCIL_EINVAL, "unknown storage %d", storage);
     if (storage != STENCIL_F32 && anchor_m < 1)
         return fail(STENCIL_EINVAL, "anchor_m must be >= 1 for low-precision storage");
@@ -193,10 +193,16 @@ int stencil_plan_query(stencil_plan_t plan, int *K, int tile[3], int *vec,
         if (plan->storage == STENCIL_F32) {
             *bytes_per_cell_step = 8.0 / plan->K;
         } else {
-            // per window of m steps: G pass 8 B, encode 6 B, m-1 delta passes of
-            // 6 B (read D and G, write D), re-anchor 10 B
             const double m = plan->anchor_m;
-            *bytes_per_cell_step = (6.0 * m + 18.0) / m;
+            if (plan->storage == STENCIL_F16 || plan->storage == STENCIL_BF16) {
+                // per window of m steps: G pass 8 B, encode 6 B, m-1 delta passes
+                // of 6 B (read D and G, write D), re-anchor 10 B
+                *bytes_per_cell_step = (6.0 * m + 18.0) / m;
+            } else {
+                // per window: tile maxima 4 B, encode 6 B, m-1 state passes of
+                // 4 B, decode 6 B, FP32 anchor step 8 B
+                *bytes_per_cell_step = (4.0 * m + 20.0) / m;
+            }
         }
     }
     return STENCIL_OK;

@@ -10,6 +10,14 @@
 //               D = encode(S decode(D) + decode(G16)), records max|decoded|
 //   A   = A + decode(D)      (the last window writes `out` instead)
 // s1 = sum |c| bounds one step's growth, so codes never leave +-2^14.
+//
+// The scaled-state form (STENCIL_F16_SCALED / STENCIL_BF16_SCALED) keeps the
+// state itself as codes between FP32 anchor steps.  Per window of m steps:
+//   eQ  from max|A| per tile;  Q = encode(A)
+//   m-1 times:  e' from the bound  s1*max_{27 nbr tiles}|Q|
+//               Q = encode(S decode(Q)), records max|decoded|
+//   A   = S decode(Q)        one FP32 step (the anchor; the last window
+//                            writes `out`)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,10 +99,83 @@ void lowp_release(stencil_plan_s *p) {
     p->lowp = nullptr;
 }
 
+namespace {
+
+// The scaled-state schedule (see the top of this file).
+hipError_t scaled_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
+                          hipStream_t st) {
+    LowpState *s = p->lowp;
+    const int codec = p->storage == STENCIL_F16_SCALED ? kCodecF16 : kCodecBF16;
+    const int nx = (int)p->nx, ny = (int)p->ny, nz = (int)p->nz;
+    float *A = p->scratch;
+    LowpArgs a{};
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.nw = p->s3_rows;
+    a.wl = p->s3_lanes;
+    a.lz = p->s3_lz;
+    a.tnx = s->tnx;
+    a.tny = s->tny;
+    a.tnz = s->tnz;
+    a.cf = p->cf;
+    // the bound has no G term: its table stays zero
+    LP_TRY(lowp_fill_u32(s->max_g16, s->ntiles, 0u, st));
+    // FP32 state at the window start (read with 16-byte vector loads)
+    const float *cur = in;
+    if ((uintptr_t)in & 15) {
+        LP_TRY(hipMemcpyAsync(A, in, (size_t)p->ncells * sizeof(float), hipMemcpyDeviceToDevice, st));
+        cur = A;
+    }
+    int64_t t = 0;
+    while (t < steps) {
+        const int64_t w = std::min<int64_t>(p->anchor_m, steps - t);
+        // exact scales from max|state|, then Q = encode(state)
+        LP_TRY(lowp_fill_u32(s->max_g32, s->ntiles, 0u, st));
+        LP_TRY(lowp_tile_max(cur, s->max_g32, nx, ny, nz, s->tnx, s->tny, st));
+        LP_TRY(lowp_exponents_from_max(s->max_g32, s->ntiles, s->e_g, st));
+        LP_TRY(lowp_fill_u32(s->max_d[0], s->ntiles, 0u, st));
+        LP_TRY(lowp_encode(codec, cur, s->e_g, s->g16, s->max_d[0], nx, ny, nz, s->tnx, s->tny, st));
+        const uint16_t *q = s->g16;
+        const int *e_q = s->e_g;
+        const unsigned *max_q = s->max_d[0];
+        for (int64_t j = 1; j < w; ++j) {
+            const int o = (int)(j & 1);
+            LP_TRY(lowp_exponents_from_bound(max_q, s->max_g16, s->s1, s->tnx, s->tny, s->tnz,
+                                             s->e_d[o], st));
+            unsigned *mo = o ? s->max_d[1] : s->max_g32;  // not the table being read
+            LP_TRY(lowp_fill_u32(mo, s->ntiles, 0u, st));
+            a.d_in = q;
+            a.e_in = e_q;
+            a.g = q;  // unused (no G term)
+            a.e_g = e_q;
+            a.d_out = s->d16[o];
+            a.e_out = s->e_d[o];
+            a.max_out = mo;
+            LP_TRY(launch_pass(p, a, kScaledPass + codec, st));
+            q = s->d16[o];
+            e_q = s->e_d[o];
+            max_q = mo;
+        }
+        t += w;
+        // anchor: one FP32 step from the decoded state
+        float *dst = t < steps ? A : out;
+        float *tmp = t < steps ? out : A;
+        LP_TRY(lowp_add_decoded(codec, nullptr, q, e_q, tmp, nx, ny, nz, s->tnx, s->tny, st));
+        LP_TRY(plan_launch_pass(p, 1, tmp, dst, st));
+        cur = A;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 hipError_t lowp_enqueue(const stencil_plan_s *p, const float *in, float *out, int64_t steps,
                         hipStream_t st) {
     const size_t bytes = (size_t)p->ncells * sizeof(float);
     if (steps == 0) return hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, st);
+    if (p->storage == STENCIL_F16_SCALED || p->storage == STENCIL_BF16_SCALED)
+        return scaled_enqueue(p, in, out, steps, st);
     LowpState *s = p->lowp;
     const int codec = p->storage;  // STENCIL_F16 == kCodecF16, STENCIL_BF16 == kCodecBF16
     const int nx = (int)p->nx, ny = (int)p->ny, nz = (int)p->nz;

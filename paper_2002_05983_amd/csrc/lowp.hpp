@@ -68,6 +68,10 @@ struct LowpArgs {
     Coefs cf;
 };
 
+// mode 0: G pass (FP32 in/out); mode kCodecF16/kCodecBF16: delta pass
+// D' = encode(S decode(D) + decode(G)); mode kScaledPass + codec: state pass
+// Q' = encode(S decode(Q)) (no G term).
+constexpr int kScaledPass = 2;
 hipError_t launch_lowp3d_r1(const LowpArgs &a, int mode, hipStream_t s);
 hipError_t launch_lowp3d_r2(const LowpArgs &a, int mode, hipStream_t s);
 hipError_t launch_lowp3d_r3(const LowpArgs &a, int mode, hipStream_t s);
@@ -82,7 +86,10 @@ hipError_t lowp_exponents_from_bound(const unsigned *max_d, const unsigned *max_
 hipError_t lowp_encode(int codec, const float *g32, const int *e_g, uint16_t *g16,
                        unsigned *max_g16, int nx, int ny, int nz, int tnx, int tny,
                        hipStream_t s);
-// out = a + decode(d)  (out may alias a)
+// max |x| per tile of an FP32 field (into maxv, which must start at 0)
+hipError_t lowp_tile_max(const float *x32, unsigned *maxv, int nx, int ny, int nz, int tnx, int tny,
+                         hipStream_t s);
+// out = a + decode(d), or decode(d) when a is null  (out may alias a)
 hipError_t lowp_add_decoded(int codec, const float *a, const uint16_t *d, const int *e_d,
                             float *out, int nx, int ny, int nz, int tnx, int tny, hipStream_t s);
 

@@ -11,6 +11,8 @@
 //   mode 0  G pass:  G32 = S A - A  (FP32 in, FP32 out), per-tile max|G|
 //   mode 1  D pass:  D' = encode(S decode(D) + decode(G)) with FP16 codes
 //   mode 2  D pass:  the same with BF16 codes
+//   mode 3/4 state pass of the scaled-state form: Q' = encode(S decode(Q))
+//           with FP16/BF16 codes (the D pass without its G term)
 // Every value of the window is FP32; each cell is c_C*f_C followed by one
 // FMA per neighbour in coefficient order, then (D pass) one FP32 add of G.
 // Codes are decoded when their plane enters the window; the exponents of a
@@ -39,7 +41,7 @@ __device__ __forceinline__ void lds_read_row4(const float *row, int lr, float (&
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 
-template <int R, int WL, int MODE>
+template <int R, int WL, int MODE, bool HAS_G>
 __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, int ntx, int nty) {
     constexpr int P = 2 * R + 1;   // window planes
     // raw rings (input codes / floats and G codes): NR planes in flight
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     static_for<0, NR - 1>([&](auto phc) STAR_INLINE {
         constexpr int PH = decltype(phc)::value;
         load_raw(zstart + PH, raw[PH]);
-        if constexpr (!FP32_IN) load_g(zstart - R + PH, graw[PH]);
+        if constexpr (HAS_G) load_g(zstart - R + PH, graw[PH]);
     });
 
     auto step_plane = [&](auto phc, int n) STAR_INLINE {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         // prefetch into the slot whose plane the previous iteration consumed
         constexpr int QN = (QH + NR - 1) % NR;
         load_raw(zl + NR - 1, raw[QN]);
-        if constexpr (!FP32_IN) load_g(r + NR - 1, graw[QN]);
+        if constexpr (HAS_G) load_g(r + NR - 1, graw[QN]);
         // the centre plane (entered the window R iterations ago) to LDS
         lds_write_row4(lds_row(b, trow), lr, win[(PH - R + P) % P]);
         __syncthreads();
@@ -255,13 +257,13 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
             const auto st = buffer_rsrc(a.g_out + (size_t)clampi(r, nz) * plane, (int)(plane * 4));
             buffer_store4(st, masked_offset((yc * nx + col0) * 4, ok), g[0], g[1], g[2], g[3]);
         } else {
-            float gv[VEC];
-            decode4(graw[QH], exponent(1, r), gv);
+            float gv[VEC] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (HAS_G) decode4(graw[QH], exponent(1, r), gv);
             const int eo = exponent(2, r);
             uint32_t q[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                q[e] = encode_code<MODE>(acc[e] + gv[e], eo);
+                q[e] = encode_code<MODE>(HAS_G ? acc[e] + gv[e] : acc[e], eo);
                 runmax = fmaxf(runmax, fabsf(decode_code<MODE>(q[e], eo)));
             }
             const auto st = buffer_rsrc(a.d_out + (size_t)clampi(r, nz) * plane, (int)(plane * 2));
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         atomicMax(a.max_out + tile_xy + (z0 >> kTileShift) * tile_zstride, __float_as_uint(runmax_all));
 }
 
-template <int WL, int MODE>
+template <int WL, int MODE, bool HAS_G>
 hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
     constexpr int R = STAR_R;
     constexpr int W = WL * VEC;
@@ -306,7 +308,7 @@ hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
     const size_t lds = (size_t)2 * nt * W * sizeof(float) + etab;
     if (blocks > ((int64_t)1 << 30) || lds > 160 * 1024) return hipErrorInvalidValue;
     if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    auto kern = lowp3d_step<R, WL, MODE>;
+    auto kern = lowp3d_step<R, WL, MODE, HAS_G>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -324,13 +326,17 @@ hipError_t STAR_CAT(launch_lowp3d_r, STAR_R)(const LowpArgs &a, int mode, hipStr
     // one z-segment per storage tile (the kernel publishes one maximum per lane)
     if (a.lz != (1 << kTileShift) || a.nx < 4 || a.ny < 1 || a.nz < 1) return hipErrorInvalidValue;
     if (a.wl == 64) {
-        if (mode == 0) return launch_m<64, 0>(a, stream);
-        if (mode == kCodecF16) return launch_m<64, kCodecF16>(a, stream);
-        if (mode == kCodecBF16) return launch_m<64, kCodecBF16>(a, stream);
+        if (mode == 0) return launch_m<64, 0, false>(a, stream);
+        if (mode == kCodecF16) return launch_m<64, kCodecF16, true>(a, stream);
+        if (mode == kCodecBF16) return launch_m<64, kCodecBF16, true>(a, stream);
+        if (mode == kScaledPass + kCodecF16) return launch_m<64, kCodecF16, false>(a, stream);
+        if (mode == kScaledPass + kCodecBF16) return launch_m<64, kCodecBF16, false>(a, stream);
     } else if (a.wl == 32) {
-        if (mode == 0) return launch_m<32, 0>(a, stream);
-        if (mode == kCodecF16) return launch_m<32, kCodecF16>(a, stream);
-        if (mode == kCodecBF16) return launch_m<32, kCodecBF16>(a, stream);
+        if (mode == 0) return launch_m<32, 0, false>(a, stream);
+        if (mode == kCodecF16) return launch_m<32, kCodecF16, true>(a, stream);
+        if (mode == kCodecBF16) return launch_m<32, kCodecBF16, true>(a, stream);
+        if (mode == kScaledPass + kCodecF16) return launch_m<32, kCodecF16, false>(a, stream);
+        if (mode == kScaledPass + kCodecBF16) return launch_m<32, kCodecBF16, false>(a, stream);
     }
     return hipErrorInvalidValue;
 }

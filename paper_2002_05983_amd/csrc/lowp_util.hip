@@ -84,6 +84,26 @@ __global__ __launch_bounds__(256) void encode_k(const float *__restrict__ g32, c
     if ((lane & 15) == 0 && in) atomicMax(maxv + t, __float_as_uint(m));
 }
 
+__global__ __launch_bounds__(256) void tile_max_k(const float *__restrict__ x32, unsigned *__restrict__ maxv,
+                                                  int nx, int ny, int nz, int tnx, int tny) {
+    const int lane = threadIdx.x & 63;
+    const Chunk c = chunk_of(nx, ny, nz, blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (!c.live) return;
+    const int x = c.x0 + lane * 4;
+    const bool in = x < nx;
+    const int t = ((c.z >> kTileShift) * tny + (c.y0 >> kTileShift)) * tnx + (min(x, nx - 4) >> kTileShift);
+    float m = 0.0f;
+    if (in) {
+        for (int y = c.y0; y < c.y1; ++y) {
+            const float4 v = *reinterpret_cast<const float4 *>(x32 + ((size_t)c.z * ny + y) * nx + x);
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+    }
+    for (int s = 8; s >= 1; s >>= 1) m = fmaxf(m, __shfl_xor(m, s, 16));
+    if ((lane & 15) == 0 && in) atomicMax(maxv + t, __float_as_uint(m));
+}
+
+// out = a + decode(d), or decode(d) when a is null
 template <int CODEC>
 __global__ __launch_bounds__(256) void add_decoded_k(const float *a, const uint16_t *__restrict__ d,
                                                      const int *__restrict__ e_d, float *out, int nx,
@@ -96,7 +116,7 @@ __global__ __launch_bounds__(256) void add_decoded_k(const float *a, const uint1
     const int e = e_d[((c.z >> kTileShift) * tny + (c.y0 >> kTileShift)) * tnx + (x >> kTileShift)];
     for (int y = c.y0; y < c.y1; ++y) {
         const size_t off = ((size_t)c.z * ny + y) * nx + x;
-        const float4 v = *reinterpret_cast<const float4 *>(a + off);
+        const float4 v = a ? *reinterpret_cast<const float4 *>(a + off) : make_float4(0.f, 0.f, 0.f, 0.f);
         const uint2 q = *reinterpret_cast<const uint2 *>(d + off);
         *reinterpret_cast<float4 *>(out + off) =
             make_float4(v.x + decode_code<CODEC>(q.x & 0xFFFFu, e), v.y + decode_code<CODEC>(q.x >> 16, e),
@@ -127,6 +147,13 @@ hipError_t lowp_exponents_from_bound(const unsigned *max_d, const unsigned *max_
     const int n = tnx * tny * tnz;
     hipLaunchKernelGGL(exp_from_bound, dim3((n + 255) / 256), dim3(256), 0, s, max_d, max_g, s1,
                        tnx, tny, tnz, e);
+    return hipGetLastError();
+}
+
+hipError_t lowp_tile_max(const float *x32, unsigned *maxv, int nx, int ny, int nz, int tnx, int tny,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(tile_max_k, dim3(chunk_blocks(nx, ny, nz)), dim3(256), 0, s, x32, maxv, nx, ny,
+                       nz, tnx, tny);
     return hipGetLastError();
 }
 

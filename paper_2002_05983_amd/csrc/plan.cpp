@@ -271,7 +271,10 @@ std::string plan_describe(const stencil_plan_s *p) {
     if (p->variant == STAR_S3D)
         snprintf(buf, sizeof buf,
                  "variant=%s ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d%s by=%s",
-                 p->storage == STENCIL_F32 ? "s3d" : p->storage == STENCIL_F16 ? "s3d-f16" : "s3d-bf16",
+                 p->storage == STENCIL_F32 ? "s3d"
+                 : p->storage == STENCIL_F16 ? "s3d-f16"
+                 : p->storage == STENCIL_BF16 ? "s3d-bf16"
+                 : p->storage == STENCIL_F16_SCALED ? "s3d-f16-scaled" : "s3d-bf16-scaled",
                  p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_lanes,
                  p->s3_rows, p->s3_lz,
                  p->storage == STENCIL_F32 ? "" : (" m=" + std::to_string(p->anchor_m)).c_str(),

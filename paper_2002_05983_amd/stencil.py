@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libstencil_mi355x.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EOVERFLOW = 0, -1, -2, -3, -4, -5
 BOUNDARY_CLAMP = 0
-STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "f16-scaled": 3, "bf16-scaled": 4}
 
 _lib = None
 

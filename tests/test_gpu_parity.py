@@ -236,6 +236,24 @@ def test_precision_form_matches_model_bitwise(torch, st, radius, shape):
             plan.close()
 
 
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", LOWP_SHAPES)
+def test_scaled_state_form_matches_model_bitwise(torch, st, radius, shape):
+    from oracle import precision
+    c = synth.coefficients(1400 + radius, 3, radius)
+    f = synth.sinusoid_grid(1500 + radius, max(shape), modes=4)[:shape[0], :shape[1], :shape[2]].copy()
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    for storage, codec in (("f16-scaled", precision.F16), ("bf16-scaled", precision.BF16)):
+        for m, steps, tune in ((3, 7, "wl=64"), (7, 7, "wl=32,nw=12"), (1, 2, None), (4, 9, None)):
+            plan = st.Plan(shape, radius, c, storage=storage, anchor_m=m, tune=tune)
+            plan.run(x, y, steps)
+            torch.cuda.synchronize()
+            want = precision.run_scaled(f, c, radius, steps, m, codec)
+            assert_bitwise(y.cpu().numpy(), want, f"{storage} m{m} {shape} r{radius} [{plan.describe()}]")
+            plan.close()
+
+
 def test_precision_form_error_and_speed_report(torch, st, oracle_mod):
     """Small sinusoid field: FP16/BF16 error against FP64 stays in the model's range."""
     shape = (64, 64, 128)
@@ -269,7 +287,8 @@ def _precision_reference():
 
 
 @pytest.mark.parametrize("storage,m,tol", [("f32", 0, TOL_F64), ("f16", 10, 1e-3), ("f16", 50, 1e-3),
-                                           ("bf16", 10, 1e-2), ("bf16", 50, 1e-2)])
+                                           ("bf16", 10, 1e-2), ("bf16", 50, 1e-2),
+                                           ("f16-scaled", 10, 5e-2), ("bf16-scaled", 10, 5e-1)])
 def test_precision_workload_128cube_vs_stored_fp64(torch, st, storage, m, tol):
     """1000 steps of radius 4 on the 128^3 sinusoid grid against the FP64
     oracle values stored for sampled cells (corners included)."""

@@ -100,3 +100,29 @@ def test_error_against_fp64_on_smooth_field(oracle_mod, codec, m, tol):
     err = oracle_mod.rel_linf(got, ref)
     assert err <= tol, err
     assert err > 0
+
+
+@pytest.mark.parametrize("codec", [precision.F16, precision.BF16])
+def test_scaled_state_constant_field_is_exact(codec):
+    c = np.array([4 / 16] + [1 / 16] * 12, dtype=np.float32)  # dyadic, sums to 1
+    f = np.full((9, 10, 12), 0.625, dtype=np.float32)
+    for m in (1, 4, 20):
+        np.testing.assert_array_equal(precision.run_scaled(f, c, 2, 9, m, codec), f)
+
+
+# Observed on the 40^3, 4-mode field: the scaled state re-rounds the whole
+# state every step, so its error does not depend on m: FP16 3.2e-4, BF16
+# 4.0e-3 for m = 1, 10, 50.  Bounds ~3x.
+@pytest.mark.parametrize("codec,tol", [(precision.F16, 1e-3), (precision.BF16, 1.2e-2)])
+def test_scaled_state_error_against_fp64(oracle_mod, codec, tol):
+    n, radius, steps = 40, 4, 60
+    f = synth.sinusoid_grid(5, n, modes=4)
+    c = synth.coefficients(6, 3, radius)
+    ref = oracle_mod.star_run_f64(f, c, radius, steps)
+    errs = [oracle_mod.rel_linf(precision.run_scaled(f, c, radius, steps, m, codec), ref)
+            for m in (1, 10)]
+    assert all(0 < e <= tol for e in errs), errs
+    # with m = 1 the anchored delta stores only one step's change: far more
+    # accurate than re-rounding the whole state
+    d1 = oracle_mod.rel_linf(precision.run(f, c, radius, steps, 1, codec), ref)
+    assert d1 < errs[0] / 5, (d1, errs[0])
