@@ -11,22 +11,25 @@ order):
   For each window of m steps (the last may be shorter):
     G   = fl32(S A - A)                      S = one step of Eq. (1)
     eG  = tile exponents of max|G| per tile; G16 = encode(G)
-    D   = G16
+    D   = G16,  MD = max|G| per tile
     repeat (window - 1) times:
-      e   = tile exponents of  s1 * max_{27 neighbour tiles} max|dec D|
-                               + max|dec G16|,   s1 = sum_k |c_k|
-      D   = encode(fl32(S dec(D) + dec(G16)), e)
+      e   = tile exponents of  s1 * max_{27 neighbour tiles} MD
+                               + max|G|,   s1 = sum_k |c_k|
+      V   = fl32(S dec(D) + dec(G16)),  MD = max|V| per tile
+      D   = encode(V, e)
     A = fl32(A + dec(D))
   result = A
+(the maxima are taken before rounding to codes)
 
 The scaled-state form (a second reading of the same storage) keeps the
 state itself as codes between FP32 anchor steps:
 
   For each window of m steps (the last may be shorter):
-    eQ = tile exponents of max|A| per tile;  Q = encode(A, eQ)
+    eQ = tile exponents of max|A| per tile;  Q = encode(A, eQ);  MQ = max|A|
     repeat (window - 1) times:
-      e   = tile exponents of  s1 * max_{27 neighbour tiles} max|dec Q|
-      Q   = encode(fl32(S dec(Q)), e)
+      e   = tile exponents of  s1 * max_{27 neighbour tiles} MQ
+      V   = fl32(S dec(Q)),  MQ = max|V| per tile
+      Q   = encode(V, e)
     A = fl32(S dec(Q))                       one FP32 step (the anchor)
   result = A
 
@@ -139,18 +142,17 @@ def run(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
     while t < steps:
         w = min(m, steps - t)
         G = (step(A) - A).astype(np.float32)
-        eG = exponents(tile_max(G))
+        max_g = tile_max(G)
+        eG = exponents(max_g)
         g16 = encode(G, per_cell(eG, shape), codec)
         gdec = decode(g16, per_cell(eG, shape), codec)
-        max_g16 = tile_max(gdec)
-        d, e_d, ddec = g16, eG, gdec
+        ddec, max_d = gdec, max_g
         for _ in range(1, w):
-            bound = s1 * neighbour_max(tile_max(ddec)).astype(np.float64) + max_g16.astype(np.float64)
-            e_new = exponents(bound)
+            bound = s1 * neighbour_max(max_d).astype(np.float64) + max_g.astype(np.float64)
+            e = exponents(bound)
             v = (step(ddec) + gdec).astype(np.float32)
-            d = encode(v, per_cell(e_new, shape), codec)
-            e_d = e_new
-            ddec = decode(d, per_cell(e_d, shape), codec)
+            max_d = tile_max(v)
+            ddec = decode(encode(v, per_cell(e, shape), codec), per_cell(e, shape), codec)
         A = (A + ddec).astype(np.float32)
         t += w
     return A
@@ -172,12 +174,15 @@ def run_scaled(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: i
     t = 0
     while t < steps:
         w = min(m, steps - t)
-        e = exponents(tile_max(A))
+        max_q = tile_max(A)
+        e = exponents(max_q)
         qdec = decode(encode(A, per_cell(e, shape), codec), per_cell(e, shape), codec)
         for _ in range(1, w):
-            bound = s1 * neighbour_max(tile_max(qdec)).astype(np.float64)
+            bound = s1 * neighbour_max(max_q).astype(np.float64)
             e = exponents(bound)
-            qdec = decode(encode(step(qdec), per_cell(e, shape), codec), per_cell(e, shape), codec)
+            v = step(qdec)
+            max_q = tile_max(v)
+            qdec = decode(encode(v, per_cell(e, shape), codec), per_cell(e, shape), codec)
         A = step(qdec)
         t += w
     return A

@@ -61,7 +61,7 @@ struct LowpArgs {
     const int *e_out;
     const float *a_in;      // G pass input (FP32 anchor)
     float *g_out;           // G pass output (FP32 staging)
-    unsigned *max_out;      // per-tile max |value written| (float bits)
+    unsigned *max_out;      // per-tile max |value| before rounding (float bits)
     int nx, ny, nz;
     int nw, wl, lz;
     int tnx, tny, tnz;      // storage tiles per axis
@@ -82,10 +82,9 @@ hipError_t lowp_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 hipError_t lowp_exponents_from_max(const unsigned *maxv, int ntiles, int *e, hipStream_t s);
 hipError_t lowp_exponents_from_bound(const unsigned *max_d, const unsigned *max_g, double s1,
                                      int tnx, int tny, int tnz, int *e, hipStream_t s);
-// G16 = encode(G32) with per-tile exponents e_g; max_g16 = max |decoded| per tile.
-hipError_t lowp_encode(int codec, const float *g32, const int *e_g, uint16_t *g16,
-                       unsigned *max_g16, int nx, int ny, int nz, int tnx, int tny,
-                       hipStream_t s);
+// G16 = encode(G32) with per-tile exponents e_g.
+hipError_t lowp_encode(int codec, const float *g32, const int *e_g, uint16_t *g16, int nx, int ny,
+                       int nz, int tnx, int tny, hipStream_t s);
 // max |x| per tile of an FP32 field (into maxv, which must start at 0)
 hipError_t lowp_tile_max(const float *x32, unsigned *maxv, int nx, int ny, int nz, int tnx, int tny,
                          hipStream_t s);

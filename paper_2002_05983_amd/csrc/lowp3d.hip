@@ -18,7 +18,8 @@
 // Codes are decoded when their plane enters the window; the exponents of a
 // lane's storage tile are re-read only when the z-tile changes.  The output
 // tile exponents were fixed before the pass from a bound on |D'|, and the
-// pass records max|decoded value| per output tile for the next bound.
+// pass records max|value| (before rounding to a code) per output tile for
+// the next bound.
 #include "lowp.hpp"
 
 #ifndef STAR_R
@@ -41,11 +42,17 @@ __device__ __forceinline__ void lds_read_row4(const float *row, int lr, float (&
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
 
-template <int R, int WL, int MODE, bool HAS_G>
+// Raw rings (input codes or floats, and G codes) of NR planes: NR - 1
+// planes in flight ahead of the one entering the window.
+template <int R>
+constexpr int default_ring() {
+    constexpr int P = 2 * R + 1;
+    return (P == 9) ? 3 : (P < 4 ? P : 4);
+}
+
+template <int R, int WL, int MODE, bool HAS_G, int NR>
 __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, int ntx, int nty) {
     constexpr int P = 2 * R + 1;   // window planes
-    // raw rings (input codes / floats and G codes): NR planes in flight
-    constexpr int NR = (P == 9) ? 3 : (P < 4 ? P : 4);
     constexpr int U = P * NR / gcd_i(P, NR);  // planes per unrolled loop trip
     constexpr int RPW = 64 / WL;
     constexpr int W = WL * VEC;
@@ -170,17 +177,46 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) win[p][e] = 0.0f;
-    // z-segments are exactly one 64-plane storage tile (the launcher fixes
-    // lz = 64), so a lane's running maximum covers one output tile and is
-    // published once, after the plane loop.
+    // z-segments are whole 64-plane storage tiles (the launcher checks lz),
+    // so a lane's running maximum is published at each tile's last plane.
     float runmax = 0.0f, runmax_all = 0.0f;
 
-    // NR-1 planes ahead; the last slot is filled by the first iteration
-    static_for<0, NR - 1>([&](auto phc) STAR_INLINE {
+    // The input ring runs NR planes ahead: a slot is refilled right after
+    // its plane entered the window.  The G ring is consumed at the end of a
+    // step, so it runs NR-1 planes ahead and its last slot is filled by the
+    // first iteration.
+    static_for<0, NR>([&](auto phc) STAR_INLINE {
         constexpr int PH = decltype(phc)::value;
         load_raw(zstart + PH, raw[PH]);
-        if constexpr (HAS_G) load_g(zstart - R + PH, graw[PH]);
+        if constexpr (HAS_G) {
+            if constexpr (PH < NR - 1) {
+                if (!load_only) load_g(zstart - R + PH, graw[PH]);
+            }
+        }
     });
+
+    // Publish the running maxima of the output tile holding plane rz: one
+    // atomic per wavefront and tile (the lanes of a tile reduce first;
+    // non-negative floats order as integers).  Wave-uniform control flow.
+    auto publish = [&](int rz) STAR_INLINE {
+        const bool has = row_out && col0 >= out_lo && col0 + VEC <= out_hi;
+        const int tile = has ? tile_xy + (rz >> kTileShift) * tile_zstride : -1;
+        const unsigned v = __float_as_uint(runmax_all);
+        bool done = !has;
+        for (;;) {  // one trip per distinct tile among the lanes (at most 64)
+            const uint64_t act = __ballot(!done);
+            if (act == 0) break;
+            const int leader = __builtin_ctzll(act);
+            const int t0 = __builtin_amdgcn_readlane(tile, leader);
+            const bool grp = !done && tile == t0;
+            unsigned m = grp ? v : 0u;
+#pragma unroll
+            for (int sh = 32; sh >= 1; sh >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, sh));
+            if (lane == leader) atomicMax(a.max_out + t0, m);
+            done = done || grp;
+        }
+        runmax_all = 0.0f;
+    };
 
     auto step_plane = [&](auto phc, int n) STAR_INLINE {
         constexpr int PH = decltype(phc)::value % P;   // window slot
@@ -188,29 +224,26 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         const int zl = zstart + n;  // plane entering the window
         const int r = zl - R;       // plane produced
         const int b = n & 1;
-        // prefetch into the slot whose plane the previous iteration consumed
+        // The entering plane (loaded NR iterations ago) takes the window slot
+        // of the plane that left it; its raw slot is refilled at once.
+        if constexpr (FP32_IN) {
+            win[PH][0] = raw[QH].x; win[PH][1] = raw[QH].y;
+            win[PH][2] = raw[QH].z; win[PH][3] = raw[QH].w;
+        } else {
+            decode4(raw[QH], exponent(0, min(zl, zlast)), win[PH]);
+        }
+        xfix(win[PH]);
+        load_raw(zl + NR, raw[QH]);
+        // G of the plane produced NR-1 steps from now, into the slot the
+        // previous step consumed
         constexpr int QN = (QH + NR - 1) % NR;
-        load_raw(zl + NR - 1, raw[QN]);
-        if constexpr (HAS_G) load_g(r + NR - 1, graw[QN]);
+        if constexpr (HAS_G) {
+            if (!load_only) load_g(r + NR - 1, graw[QN]);  // only computing rows use G
+        }
         // the centre plane (entered the window R iterations ago) to LDS
         lds_write_row4(lds_row(b, trow), lr, win[(PH - R + P) % P]);
         __syncthreads();
-        // The entering plane is first needed by this step's very last term
-        // (A_R), so it is decoded just before it: its load overlaps the rest
-        // of the step.
-        auto enter = [&]() STAR_INLINE {
-            if constexpr (FP32_IN) {
-                win[PH][0] = raw[QH].x; win[PH][1] = raw[QH].y;
-                win[PH][2] = raw[QH].z; win[PH][3] = raw[QH].w;
-            } else {
-                decode4(raw[QH], exponent(0, min(zl, zlast)), win[PH]);
-            }
-            xfix(win[PH]);
-        };
-        if (load_only) {
-            enter();
-            return;
-        }
+        if (load_only) return;
         constexpr int CS = (PH - R + P) % P;
         float left[R + 1], right[R + 1];
 #pragma unroll
@@ -240,7 +273,6 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
                     acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kA, i)], win[(CS + i) % P][e], acc[e]);
             }
         }
-        enter();  // win[(CS + R) % P] is the entering plane
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
             acc[e] = __builtin_fmaf(a.cf.c[coef_index<3>(kA, R)], win[(CS + R) % P][e], acc[e]);
@@ -263,8 +295,9 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
             uint32_t q[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                q[e] = encode_code<MODE>(HAS_G ? acc[e] + gv[e] : acc[e], eo);
-                runmax = fmaxf(runmax, fabsf(decode_code<MODE>(q[e], eo)));
+                const float v = HAS_G ? acc[e] + gv[e] : acc[e];
+                q[e] = encode_code<MODE>(v, eo);
+                runmax = fmaxf(runmax, fabsf(v));  // the value before rounding
             }
             const auto st = buffer_rsrc(a.d_out + (size_t)clampi(r, nz) * plane, (int)(plane * 2));
             const v2i packed = {(int)(q[0] | (q[1] << 16)), (int)(q[2] | (q[3] << 16))};
@@ -274,6 +307,8 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         if (!ok) runmax = 0.0f;  // only cells this lane writes count
         runmax_all = fmaxf(runmax_all, runmax);
         runmax = 0.0f;
+        // a segment may span several storage tiles in z
+        if (((r + 1) & ((1 << kTileShift) - 1)) == 0 && r >= z0 && r < z1 - 1) publish(r);
     };
 
     int n0 = 0;
@@ -283,11 +318,10 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     static_for<0, U>([&](auto phc) STAR_INLINE {
         if (n0 + decltype(phc)::value < niter) step_plane(phc, n0 + decltype(phc)::value);
     });
-    if (!load_only && row_out && col0 >= out_lo && col0 + VEC <= out_hi)
-        atomicMax(a.max_out + tile_xy + (z0 >> kTileShift) * tile_zstride, __float_as_uint(runmax_all));
+    if (!load_only) publish(z1 - 1);
 }
 
-template <int WL, int MODE, bool HAS_G>
+template <int WL, int MODE, bool HAS_G, int NR>
 hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
     constexpr int R = STAR_R;
     constexpr int W = WL * VEC;
@@ -308,7 +342,7 @@ hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
     const size_t lds = (size_t)2 * nt * W * sizeof(float) + etab;
     if (blocks > ((int64_t)1 << 30) || lds > 160 * 1024) return hipErrorInvalidValue;
     if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    auto kern = lowp3d_step<R, WL, MODE, HAS_G>;
+    auto kern = lowp3d_step<R, WL, MODE, HAS_G, NR>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -317,27 +351,32 @@ hipError_t launch_m(const LowpArgs &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int WL, int NR>
+hipError_t launch_mode(const LowpArgs &a, int mode, hipStream_t stream) {
+    if (mode == 0) return launch_m<WL, 0, false, NR>(a, stream);
+    if (mode == kCodecF16) return launch_m<WL, kCodecF16, true, NR>(a, stream);
+    if (mode == kCodecBF16) return launch_m<WL, kCodecBF16, true, NR>(a, stream);
+    if (mode == kScaledPass + kCodecF16) return launch_m<WL, kCodecF16, false, NR>(a, stream);
+    if (mode == kScaledPass + kCodecBF16) return launch_m<WL, kCodecBF16, false, NR>(a, stream);
+    return hipErrorInvalidValue;
+}
+
+template <int WL>
+hipError_t launch_d(const LowpArgs &a, int mode, hipStream_t stream) {
+    return launch_mode<WL, default_ring<STAR_R>()>(a, mode, stream);
+}
+
 }  // namespace
 
 #define STAR_CAT2(a, b) a##b
 #define STAR_CAT(a, b) STAR_CAT2(a, b)
 
 hipError_t STAR_CAT(launch_lowp3d_r, STAR_R)(const LowpArgs &a, int mode, hipStream_t stream) {
-    // one z-segment per storage tile (the kernel publishes one maximum per lane)
-    if (a.lz != (1 << kTileShift) || a.nx < 4 || a.ny < 1 || a.nz < 1) return hipErrorInvalidValue;
-    if (a.wl == 64) {
-        if (mode == 0) return launch_m<64, 0, false>(a, stream);
-        if (mode == kCodecF16) return launch_m<64, kCodecF16, true>(a, stream);
-        if (mode == kCodecBF16) return launch_m<64, kCodecBF16, true>(a, stream);
-        if (mode == kScaledPass + kCodecF16) return launch_m<64, kCodecF16, false>(a, stream);
-        if (mode == kScaledPass + kCodecBF16) return launch_m<64, kCodecBF16, false>(a, stream);
-    } else if (a.wl == 32) {
-        if (mode == 0) return launch_m<32, 0, false>(a, stream);
-        if (mode == kCodecF16) return launch_m<32, kCodecF16, true>(a, stream);
-        if (mode == kCodecBF16) return launch_m<32, kCodecBF16, true>(a, stream);
-        if (mode == kScaledPass + kCodecF16) return launch_m<32, kCodecF16, false>(a, stream);
-        if (mode == kScaledPass + kCodecBF16) return launch_m<32, kCodecBF16, false>(a, stream);
-    }
+    // z-segments of whole storage tiles (the kernel publishes per-tile maxima)
+    if (a.lz < 1 || a.lz % (1 << kTileShift) != 0 || a.nx < 4 || a.ny < 1 || a.nz < 1)
+        return hipErrorInvalidValue;
+    if (a.wl == 64) return launch_d<64>(a, mode, stream);
+    if (a.wl == 32) return launch_d<32>(a, mode, stream);
     return hipErrorInvalidValue;
 }
 

@@ -58,8 +58,8 @@ __device__ __forceinline__ Chunk chunk_of(int nx, int ny, int nz, int wave) {
 
 template <int CODEC>
 __global__ __launch_bounds__(256) void encode_k(const float *__restrict__ g32, const int *__restrict__ e_g,
-                                                uint16_t *__restrict__ g16, unsigned *__restrict__ maxv,
-                                                int nx, int ny, int nz, int tnx, int tny) {
+                                                uint16_t *__restrict__ g16, int nx, int ny, int nz,
+                                                int tnx, int tny) {
     const int lane = threadIdx.x & 63;
     const Chunk c = chunk_of(nx, ny, nz, blockIdx.x * 4 + (threadIdx.x >> 6));
     if (!c.live) return;
@@ -67,21 +67,15 @@ __global__ __launch_bounds__(256) void encode_k(const float *__restrict__ g32, c
     const bool in = x < nx;
     const int t = ((c.z >> kTileShift) * tny + (c.y0 >> kTileShift)) * tnx + (min(x, nx - 4) >> kTileShift);
     const int e = e_g[t];
-    float m = 0.0f;
     if (in) {
         for (int y = c.y0; y < c.y1; ++y) {
             const size_t off = ((size_t)c.z * ny + y) * nx + x;
             const float4 v = *reinterpret_cast<const float4 *>(g32 + off);
             const uint32_t q0 = encode_code<CODEC>(v.x, e), q1 = encode_code<CODEC>(v.y, e);
             const uint32_t q2 = encode_code<CODEC>(v.z, e), q3 = encode_code<CODEC>(v.w, e);
-            m = fmaxf(m, fmaxf(fmaxf(fabsf(decode_code<CODEC>(q0, e)), fabsf(decode_code<CODEC>(q1, e))),
-                               fmaxf(fabsf(decode_code<CODEC>(q2, e)), fabsf(decode_code<CODEC>(q3, e)))));
             *reinterpret_cast<uint2 *>(g16 + off) = make_uint2(q0 | (q1 << 16), q2 | (q3 << 16));
         }
     }
-    // the 16 lanes of a storage tile (64 columns) reduce, one atomic each
-    for (int s = 8; s >= 1; s >>= 1) m = fmaxf(m, __shfl_xor(m, s, 16));
-    if ((lane & 15) == 0 && in) atomicMax(maxv + t, __float_as_uint(m));
 }
 
 __global__ __launch_bounds__(256) void tile_max_k(const float *__restrict__ x32, unsigned *__restrict__ maxv,
@@ -157,15 +151,15 @@ hipError_t lowp_tile_max(const float *x32, unsigned *maxv, int nx, int ny, int n
     return hipGetLastError();
 }
 
-hipError_t lowp_encode(int codec, const float *g32, const int *e_g, uint16_t *g16, unsigned *max_g16,
-                       int nx, int ny, int nz, int tnx, int tny, hipStream_t s) {
+hipError_t lowp_encode(int codec, const float *g32, const int *e_g, uint16_t *g16, int nx, int ny,
+                       int nz, int tnx, int tny, hipStream_t s) {
     const unsigned blocks = chunk_blocks(nx, ny, nz);
     if (codec == kCodecF16)
-        hipLaunchKernelGGL(encode_k<kCodecF16>, dim3(blocks), dim3(256), 0, s, g32, e_g, g16, max_g16,
-                           nx, ny, nz, tnx, tny);
+        hipLaunchKernelGGL(encode_k<kCodecF16>, dim3(blocks), dim3(256), 0, s, g32, e_g, g16, nx, ny,
+                           nz, tnx, tny);
     else
-        hipLaunchKernelGGL(encode_k<kCodecBF16>, dim3(blocks), dim3(256), 0, s, g32, e_g, g16, max_g16,
-                           nx, ny, nz, tnx, tny);
+        hipLaunchKernelGGL(encode_k<kCodecBF16>, dim3(blocks), dim3(256), 0, s, g32, e_g, g16, nx, ny,
+                           nz, tnx, tny);
     return hipGetLastError();
 }
 

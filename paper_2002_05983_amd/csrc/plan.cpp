@@ -134,6 +134,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 p->vec = v;
             } else if (key == "wl" && p->ndim == 3) {
                 p->s3_lanes = v;
+
             } else {
                 return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
             }
@@ -153,10 +154,11 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             return star_set_error(STENCIL_EUNSUPPORTED, "3D planes must stay below 2^31 bytes");
         if (p->storage != STENCIL_F32) {
             // the low-precision passes are single-step, 4 cells per lane
-            if (p->K != 1 || (p->vec != 0 && p->vec != 4) || (p->s3_lz != 0 && p->s3_lz != 64))
-                return star_set_error(STENCIL_EINVAL, "low-precision storage runs k=1, vec=4, lz=64");
+            if (p->K != 1 || (p->vec != 0 && p->vec != 4) || p->s3_lz % 64 != 0)
+                return star_set_error(STENCIL_EINVAL,
+                                      "low-precision storage runs k=1, vec=4, lz a multiple of 64");
             p->vec = 4;
-            p->s3_lz = 64;  // one z-segment per 64^3 storage tile
+            if (p->s3_lz == 0) p->s3_lz = 256;  // z-segments of whole 64^3 storage tiles
         }
         if (p->K < 1 || p->K > max_k3d(R))
             return star_set_error(STENCIL_EINVAL, "3D k must be in 1..4/2/1/1 for R = 1..4");
@@ -277,7 +279,8 @@ std::string plan_describe(const stencil_plan_s *p) {
                  : p->storage == STENCIL_F16_SCALED ? "s3d-f16-scaled" : "s3d-bf16-scaled",
                  p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_lanes,
                  p->s3_rows, p->s3_lz,
-                 p->storage == STENCIL_F32 ? "" : (" m=" + std::to_string(p->anchor_m)).c_str(),
+                 p->storage == STENCIL_F32 ? ""
+                 : (" m=" + std::to_string(p->anchor_m)).c_str(),
                  p->tuned_by.c_str());
     else
         snprintf(buf, sizeof buf, "variant=%s ndim=%d R=%d K=%d tile=%dx%dx%d vec=%d ly=%d by=%s", v,

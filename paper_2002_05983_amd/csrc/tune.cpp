@@ -52,9 +52,9 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                     if (vec == 8 && (wl != 64 || !vec8_ok(R, K, p->nx % 4 == 0) || p->nx <= 256 ||
                                      p->storage != STENCIL_F32))
                         continue;
-                    for (int lz : {32, 64, 128}) {
+                    for (int lz : {32, 64, 128, 256}) {
                         if (lz > p->nz && lz != 32) continue;
-                        if (p->storage != STENCIL_F32 && lz != 64) continue;
+                        if (p->storage != STENCIL_F32 && lz % 64 != 0) continue;
                         snprintf(buf, sizeof buf, "k=%d,wl=%d,vec=%d,lz=%d", K, wl, vec, lz);
                         out.push_back(buf);
                     }
