@@ -62,18 +62,26 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(kernel: str):
-    """Counter-measured HBM bytes per launch of `kernel`, or None when the
-    record is missing, for another configuration, or older than the source."""
+    """Counter-measured HBM bytes per launch of `kernel`, or None when no
+    record is for this configuration or the record is older than the source.
+    Records are blocks of "key: value" lines, each opened by a "kernel:" line."""
     try:
-        rec = {}
+        recs, rec = [], None
         with open(TRAFFIC_FILE) as fh:
             for line in fh:
-                if ":" in line and not line.startswith("#"):
-                    k, v = line.split(":", 1)
-                    rec[k.strip()] = v.strip()
-        if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_source_hash():
-            return None
-        return float(rec["traffic_bytes_per_launch"])
+                if ":" not in line or line.startswith("#"):
+                    continue
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k == "kernel":
+                    rec = {}
+                    recs.append(rec)
+                if rec is not None:
+                    rec[k] = v
+        src = kernel_source_hash()
+        for rec in recs:
+            if rec.get("kernel") == kernel and rec.get("source_sha256") == src:
+                return float(rec["traffic_bytes_per_launch"])
+        return None
     except (OSError, KeyError, ValueError):
         return None
 
@@ -298,6 +306,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
     ap.add_argument("--time-steps", type=int, default=TIME_STEPS, help=argparse.SUPPRESS)
+    ap.add_argument("--config", action="append", default=[], metavar="R:TUNE", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB FP32 buffer 4 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -330,10 +339,14 @@ def main():
     coeffs = {r: synth.coefficients(1000 + r, 2, r) for r in RADII}
     x = torch.from_numpy(f0).to(dev)
     y = torch.empty_like(x)
-    plans = {r: stencil.Plan(shape, r, coeffs[r]) for r in RADII}
+    # --config R:TUNE fixes a radius's configuration (profiling runs)
+    fixed = {int(c.split(":", 1)[0]): c.split(":", 1)[1] for c in args.config}
+    plans = {r: stencil.Plan(shape, r, coeffs[r], tune=fixed.get(r)) for r in RADII}
     stream = torch.cuda.current_stream(dev)
     if not args.no_tune:
         for r in RADII:
+            if r in fixed:
+                continue
             plans[r].autotune(x, y, stream=stream)
             progress(f"2D radius {r} tuned: {plans[r].describe()}")
 

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     };
 
     Raw raw[NR];
+    int eraw[NR];  // exponent of each raw slot's plane, read from LDS with its load
     uint2 graw[NR];
     float win[P][VEC];
 #pragma unroll
@@ -188,6 +189,7 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
     static_for<0, NR>([&](auto phc) STAR_INLINE {
         constexpr int PH = decltype(phc)::value;
         load_raw(zstart + PH, raw[PH]);
+        if constexpr (!FP32_IN) eraw[PH] = exponent(0, min(zstart + PH, zlast));
         if constexpr (HAS_G) {
             if constexpr (PH < NR - 1) {
                 if (!load_only) load_g(zstart - R + PH, graw[PH]);
@@ -230,10 +232,11 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
             win[PH][0] = raw[QH].x; win[PH][1] = raw[QH].y;
             win[PH][2] = raw[QH].z; win[PH][3] = raw[QH].w;
         } else {
-            decode4(raw[QH], exponent(0, min(zl, zlast)), win[PH]);
+            decode4(raw[QH], eraw[QH], win[PH]);
         }
         xfix(win[PH]);
         load_raw(zl + NR, raw[QH]);
+        if constexpr (!FP32_IN) eraw[QH] = exponent(0, min(zl + NR, zlast));
         // G of the plane produced NR-1 steps from now, into the slot the
         // previous step consumed
         constexpr int QN = (QH + NR - 1) % NR;
