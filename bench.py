@@ -114,6 +114,27 @@ def cpu_baseline(f0, coeffs_by_r, sample_steps: int = 2):
                       f"({updates:.3e} cell updates in {t:.1f} s)"}
 
 
+def model_accuracy(plan, rows):
+    """The analytic model against the autotuner's measurements of every
+    candidate: median |predicted/measured - 1|, Spearman rank correlation,
+    and the measured rate of the model's pick over the measured best."""
+    import numpy as np
+    pred, meas = [], []
+    for cfg, g in rows:
+        try:
+            pred.append(plan.model(cfg)["GCell/s"])
+            meas.append(g)
+        except Exception:
+            continue
+    if len(meas) < 2:
+        return None
+    pred, meas = np.array(pred), np.array(meas)
+    rp, rm = pred.argsort().argsort(), meas.argsort().argsort()
+    rho = float(np.corrcoef(rp, rm)[0, 1])
+    return {"candidates": len(meas), "median_abs_err": round(float(np.median(np.abs(pred / meas - 1))), 4),
+            "spearman": round(rho, 3), "pick_over_best": round(float(meas[pred.argmax()] / meas.max()), 4)}
+
+
 def bench_3d(stencil, synth, torch, dev, side=512, time_steps=200, reps=2, tune=True):
     """3D star stencils r=1..4 on side^3 FP32 (U[0,1)), time_steps steps each."""
     shape = (side, side, side)
@@ -123,8 +144,9 @@ def bench_3d(stencil, synth, torch, dev, side=512, time_steps=200, reps=2, tune=
     rows, tot_ms = [], 0.0
     for r in RADII:
         p = stencil.Plan(shape, r, synth.coefficients(2000 + r, 3, r))
+        acc = None
         if tune:
-            p.autotune(x, y, stream=stream)
+            acc = model_accuracy(p, p.autotune(x, y, stream=stream))
         p.run(x, y, time_steps, stream=stream)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize(dev)
@@ -139,7 +161,8 @@ def bench_3d(stencil, synth, torch, dev, side=512, time_steps=200, reps=2, tune=
         rows.append({"radius": r, "ms": round(ms, 3), "GCell/s": round(gc, 1),
                      "GFLOP/s": round(gc * flop_per_cell(3, r), 1),
                      "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
-                     "config": p.describe()})
+                     "config": p.describe(), "model_GCell/s": round(p.model()["GCell/s"], 1),
+                     "model_accuracy": acc})
         p.close()
     total = x.numel() * time_steps * len(RADII) / (tot_ms / 1e3) / 1e9
     return {"workload": f"3D star stencils r=1..4, {side}^3 FP32 U[0,1), {time_steps} steps per "
@@ -343,11 +366,12 @@ def main():
     fixed = {int(c.split(":", 1)[0]): c.split(":", 1)[1] for c in args.config}
     plans = {r: stencil.Plan(shape, r, coeffs[r], tune=fixed.get(r)) for r in RADII}
     stream = torch.cuda.current_stream(dev)
+    accuracy = {}
     if not args.no_tune:
         for r in RADII:
             if r in fixed:
                 continue
-            plans[r].autotune(x, y, stream=stream)
+            accuracy[r] = model_accuracy(plans[r], plans[r].autotune(x, y, stream=stream))
             progress(f"2D radius {r} tuned: {plans[r].describe()}")
 
     def one_step(record=None):
@@ -390,7 +414,9 @@ def main():
                "GCell/s": round(gc, 1), "GFLOP/s": round(gc * flop_per_cell(2, r), 1),
                "eff_GB/s": round(gc * 8, 1), "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
                "passes": npass, "ms_per_pass": round(ms / npass, 4),
-               "config": plans[r].describe()}
+               "config": plans[r].describe(),
+               "model_GCell/s": round(plans[r].model()["GCell/s"], 1),
+               "model_accuracy": accuracy.get(r)}
         per_radius.append(row)
         if dominant is None or ms > dominant["ms"]:
             dominant = row

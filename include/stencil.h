@@ -190,13 +190,32 @@ STENCIL_API int stencil_batch_describe(stencil_batch_t batch, char *buf, size_t 
 STENCIL_API void stencil_batch_destroy(stencil_batch_t batch);
 
 /*
+ * Analytic throughput model of the plan's kernel (the GPU counterpart of the
+ * paper's performance model, Sec. V.A): a pass of K fused steps is bounded by
+ * the largest of its HBM time (bytes / effective bandwidth), its VALU issue
+ * time and (3D) its per-plane critical path, plus a launch cost.
+ *   config  NULL for the plan's own configuration, or a configuration string
+ *           as for stencil_plan_ex's tune (validated the same way).
+ *   out     out[0] predicted GCell/s, out[1] HBM time per pass (us),
+ *           out[2] VALU time per pass (us), out[3] time of the sequential
+ *           path per pass (us: 3D planes streamed per CU; 2D rows streamed
+ *           per wavefront when wavefronts are fewer than SIMDs).
+ * Host-only (no device call).  Errors: EINVAL, EUNSUPPORTED (the naive
+ * variant and the low-precision forms are not modelled).
+ */
+STENCIL_API int stencil_plan_model(stencil_plan_t plan, const char *config, double out[4]);
+
+/*
  * Measured autotuning (the empirical counterpart of the paper's model-guided
  * parameter search, Sec. V.A): times every feasible configuration of the
  * plan -- temporal degree K, segment length, lanes and cells per row -- on
  * the caller's grids at the plan's real shape, with HIP events on `stream`,
  * keeps the fastest in the plan and, when the environment variable
  * STENCIL_TUNE_CACHE names a writable file, records it there; later plans
- * of the same problem (ndim, radius, storage, dims) read it back.
+ * of the same problem (ndim, radius, storage, dims) read it back, and plans
+ * of the same size class (ceil(log2 side) per axis) fall back to it.  When
+ * STENCIL_TUNE_TOP=N (N >= 1) is set, only the N candidates the analytic
+ * model (stencil_plan_model) ranks highest are timed.
  *   in, out  device grids as for stencil_run (`out` is overwritten).
  *   report   optional host buffer (NULL allowed) for a text table of the
  *            candidates: "<config> <GCell/s>" per line, best first.

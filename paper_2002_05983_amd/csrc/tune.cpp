@@ -32,6 +32,22 @@ std::string cache_key(const stencil_plan_s *p) {
     return buf;
 }
 
+// The size class of a problem: ceil(log2 side) per axis.  A plan with no
+// entry for its exact dims takes the configuration recorded for its class.
+int log2_ceil(int64_t v) {
+    int k = 0;
+    while (((int64_t)1 << k) < v) ++k;
+    return k;
+}
+
+std::string class_key(const stencil_plan_s *p) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "ndim=%d R=%d storage=%d class=%dx%dx%d arch=%s", p->ndim, p->radius,
+             p->storage, log2_ceil(p->nx), log2_ceil(p->ny), log2_ceil(p->nz),
+             tune_arch_name(p->device).c_str());
+    return buf;
+}
+
 // Every configuration worth timing for this problem.
 std::vector<std::string> candidates(const stencil_plan_s *p) {
     std::vector<std::string> out;
@@ -52,11 +68,16 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                     if (vec == 8 && (wl != 64 || !vec8_ok(R, K, p->nx % 4 == 0) || p->nx <= 256 ||
                                      p->storage != STENCIL_F32))
                         continue;
+                    const bool lowp = p->storage != STENCIL_F32;
                     for (int lz : {32, 64, 128, 256}) {
-                        if (lz > p->nz && lz != 32) continue;
-                        if (p->storage != STENCIL_F32 && lz % 64 != 0) continue;
-                        snprintf(buf, sizeof buf, "k=%d,wl=%d,vec=%d,lz=%d", K, wl, vec, lz);
-                        out.push_back(buf);
+                        if (lz > p->nz && lz != (lowp ? 64 : 32)) continue;
+                        if (lowp && lz % 64 != 0) continue;
+                        for (int nw : {16, 12, 8}) {
+                            if (nw * (64 / wl) <= 2 * K * R) continue;  // no output rows left
+                            snprintf(buf, sizeof buf, "k=%d,wl=%d,vec=%d,lz=%d,nw=%d", K, wl, vec, lz,
+                                     nw);
+                            out.push_back(buf);
+                        }
                     }
                 }
     }
@@ -107,7 +128,7 @@ void tune_cache_put(const std::string &key, const std::string &config, double gc
 }
 
 bool tune_cache_lookup(const stencil_plan_s *p, std::string &config) {
-    return tune_cache_get(cache_key(p), config);
+    return tune_cache_get(cache_key(p), config) || tune_cache_get(class_key(p), config);
 }
 
 extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float *out, char *report,
@@ -128,7 +149,26 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float
         double gcells;
     };
     std::vector<Result> results;
-    for (const std::string &cand : candidates(plan)) {
+    std::vector<std::string> cands = candidates(plan);
+    // model-guided pruning: time only the N best predicted candidates
+    if (const char *top = getenv("STENCIL_TUNE_TOP")) {
+        const long n = strtol(top, nullptr, 10);
+        if (n >= 1 && plan->storage == STENCIL_F32 && (size_t)n < cands.size()) {
+            std::vector<std::pair<double, std::string>> ranked;
+            for (const std::string &c : cands) {
+                double m[4] = {0, 0, 0, 0};
+                if (stencil_plan_model(plan, c.c_str(), m) == STENCIL_OK) ranked.push_back({m[0], c});
+            }
+            std::stable_sort(ranked.begin(), ranked.end(),
+                             [](const std::pair<double, std::string> &a,
+                                const std::pair<double, std::string> &b) { return a.first > b.first; });
+            if (!ranked.empty()) {
+                cands.clear();
+                for (size_t i = 0; i < ranked.size() && i < (size_t)n; ++i) cands.push_back(ranked[i].second);
+            }
+        }
+    }
+    for (const std::string &cand : cands) {
         stencil_plan_s trial = saved;
         trial.scratch = saved.scratch;
         if (plan_configure(&trial, cand.c_str()) != STENCIL_OK) continue;
@@ -168,6 +208,7 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float
     }
     plan->tuned_by = "autotune";
     tune_cache_put(cache_key(plan), results[0].config, results[0].gcells);
+    tune_cache_put(class_key(plan), results[0].config, results[0].gcells);
     if (report && report_len > 0) {
         std::string r;
         for (const Result &x : results) {

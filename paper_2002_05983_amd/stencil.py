@@ -45,6 +45,7 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_double)]),
     "stencil_plan_describe": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "stencil_plan_autotune": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_char_p, ctypes.c_size_t, _vp]),
+    "stencil_plan_model": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]),
     "stencil_reduce_f64": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                           _vp]),
     "stencil_plan_destroy": (None, [_vp]),
@@ -164,6 +165,12 @@ class Plan:
             cfg, g = line.rsplit(" ", 1)
             rows.append((cfg, float(g)))
         return rows
+
+    def model(self, config: str | None = None) -> dict:
+        """Analytic prediction for the plan's (or the given) configuration."""
+        out = (ctypes.c_double * 4)()
+        _check(load().stencil_plan_model(self._h, config.encode() if config else None, out))
+        return {"GCell/s": out[0], "hbm_us": out[1], "valu_us": out[2], "plane_us": out[3]}
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(512)

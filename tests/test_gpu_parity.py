@@ -212,6 +212,17 @@ def test_autotune_keeps_bitwise_result_and_caches(torch, st, oracle_mod, shape, 
     assert "by=cache" in again.describe()
     assert again.query()["K"] == plan.query()["K"]
     assert table[0][0] in cache.read_text()
+    # a plan of another shape in the same size class (ceil(log2 side) per
+    # axis) falls back to the class's entry, and still computes exactly
+    sib_shape = tuple(n - max(1, n // 40) for n in shape)
+    sib = st.Plan(sib_shape, radius, c)
+    assert "by=cache" in sib.describe() and sib.query()["K"] == plan.query()["K"]
+    fs = synth.grid_uniform(952, sib_shape)
+    xs = torch.from_numpy(fs).cuda()
+    ys = torch.empty_like(xs)
+    sib.run(xs, ys, 5)
+    torch.cuda.synchronize()
+    assert_bitwise(ys.cpu().numpy(), oracle_mod.star_run_f32(fs, c, radius, 5), "class-cached")
 
 
 # precision form: bitwise against the CPU model of the same algorithm
@@ -306,3 +317,46 @@ def test_precision_workload_128cube_vs_stored_fp64(torch, st, storage, m, tol):
     err = np.max(np.abs(vals - want)) / maxabs
     assert err <= tol, (storage, m, err)
     plan.close()
+
+
+def test_model_predictions_and_errors(torch, st):
+    p2 = st.Plan((4096, 4096), 2, synth.coefficients(3, 2, 2))
+    m = p2.model()
+    assert m["GCell/s"] > 0 and m["hbm_us"] > 0 and m["valu_us"] > 0 and m["plane_us"] == 0
+    # more fused steps move fewer bytes per step: higher predicted rate, HBM time per pass unchanged
+    assert p2.model("k=4,ly=128")["GCell/s"] > p2.model("k=1,ly=128")["GCell/s"]
+    with pytest.raises(ValueError):
+        p2.model("k=99")
+    p3 = st.Plan((64, 64, 256), 4, synth.coefficients(4, 3, 4))
+    m3 = p3.model("k=1,wl=32,lz=64")
+    assert m3["GCell/s"] > 0 and m3["plane_us"] > 0
+    pn = st.Plan((64, 64), 1, synth.coefficients(5, 2, 1), tune="naive")
+    with pytest.raises(st.StencilError):
+        pn.model()
+    for p in (p2, p3, pn):
+        p.close()
+
+
+def test_autotune_prunes_by_model(torch, st, oracle_mod, monkeypatch):
+    monkeypatch.setenv("STENCIL_TUNE_TOP", "3")
+    monkeypatch.delenv("STENCIL_TUNE_CACHE", raising=False)
+    shape, radius = (300, 1100), 3
+    c = synth.coefficients(960, 2, radius)
+    f = synth.grid_uniform(961, shape)
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    p = st.Plan(shape, radius, c)
+    rows = p.autotune(x, y)
+    assert len(rows) == 3
+    timed = {cfg for cfg, _ in rows}
+    # the three timed candidates are the model's three best
+    worst_timed = min(p.model(cfg)["GCell/s"] for cfg in timed)
+    for K in range(1, 6):
+        for ly in (64, 96, 128, 192, 256, 384):
+            cfg = f"k={K},ly={ly}"
+            if cfg not in timed and ly <= shape[0]:
+                assert p.model(cfg)["GCell/s"] <= worst_timed + 1e-9, cfg
+    p.run(x, y, 6)
+    torch.cuda.synchronize()
+    assert_bitwise(y.cpu().numpy(), oracle_mod.star_run_f32(f, c, radius, 6), "pruned autotune")
+    p.close()
