@@ -186,7 +186,7 @@ def read_precision_reference():
 
 
 def bench_precision(stencil, synth, torch, dev, side=768, time_steps=1000, radius=4,
-                    anchors=(10, 50), reps=1):
+                    anchors=(10, 50), reps=1, tune=True):
     """Precision form: FP32 against FP16/BF16 storage with re-anchoring every m
     steps, 3D radius 4 on the side^3 sinusoid grid.  Error vs the FP32 run on
     the full grid (FP64 reduction on the GPU), and vs the FP64 oracle on the
@@ -198,7 +198,8 @@ def bench_precision(stencil, synth, torch, dev, side=768, time_steps=1000, radiu
     cells = x.numel()
 
     def timed(plan, y):
-        plan.autotune(x, y, stream=stream)  # every form at its best configuration
+        if tune:
+            plan.autotune(x, y, stream=stream)  # every form at its best configuration
         plan.run(x, y, 2, stream=stream)  # warm-up
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize(dev)
@@ -471,7 +472,7 @@ def main():
         extra["3d"] = bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)
         progress(f"3D: {extra['3d']['GCell/s']} GCell/s")
     if not args.no_precision:
-        extra["precision"] = bench_precision(stencil, synth, torch, dev)
+        extra["precision"] = bench_precision(stencil, synth, torch, dev, tune=not args.no_tune)
         progress("precision form done")
     if not args.no_batch:
         extra["batch"] = bench_batch(stencil, synth, torch, dev, tune=not args.no_tune)
