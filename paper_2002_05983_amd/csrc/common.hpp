@@ -55,6 +55,15 @@ __device__ __forceinline__ float from_upper_lane(float v, float edge) {
                                                                  __builtin_bit_cast(int, v), 0x130,
                                                                  0xf, 0xf, false));
 }
+// The same shifts where the lane with no source may receive anything (zero).
+__device__ __forceinline__ float from_lower_lane_or_zero(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf,
+                                                              0xf, true));
+}
+__device__ __forceinline__ float from_upper_lane_or_zero(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf,
+                                                              0xf, true));
+}
 // Value of v in lane `lane` (wave-uniform lane index), broadcast to all lanes.
 __device__ __forceinline__ float lane_value(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));

@@ -24,7 +24,11 @@ __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ s
     const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 +
                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
-    star2d_body<R, K, M, ALIGNED>(src, dst, nx, ny, ly, wave % nstrips, wave / nstrips, cf);
+    const int strip = wave % nstrips, seg = wave / nstrips;
+    if (s2d::star2d_interior<R, K>(nx, ny, ly, strip, seg))
+        star2d_body<R, K, M, ALIGNED, false>(src, dst, nx, ny, ly, strip, seg, cf);
+    else
+        star2d_body<R, K, M, ALIGNED, true>(src, dst, nx, ny, ly, strip, seg, cf);
 }
 
 template <int K, bool AL>

@@ -39,14 +39,23 @@ constexpr int VEC = kVec2D;
 
 // Cells of one row of one stage.  q is a circular buffer of rows of the
 // stage's input (NS slots); CS is the slot of the centre row (compile-time).
-template <int R, int NS, int CS>
+// EDGE: the strip may hold the grid's border, so the lanes at the ends of
+// the wavefront take their own outermost cell as the missing neighbour;
+// otherwise those lanes hold halo columns whose values never reach the
+// output and the shifts fill them with zero.
+template <int R, int NS, int CS, bool EDGE>
 __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
                                            float (&res)[VEC]) {
     float left[R + 1], right[R + 1];
 #pragma unroll
     for (int k = 1; k <= R; ++k) {
-        left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);  // column base - k
-        right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);   // column base + VEC - 1 + k
+        if constexpr (EDGE) {
+            left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);      // column base - k
+            right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);  // column base + VEC - 1 + k
+        } else {
+            left[k] = from_lower_lane_or_zero(q[CS][VEC - k]);
+            right[k] = from_upper_lane_or_zero(q[CS][k - 1]);
+        }
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
@@ -68,8 +77,11 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
 
 // One wavefront's work: strip `strip` (TX output columns) of y-segment `seg`
 // (ly output rows) of one grid.  Wave-level: no barriers, no LDS.  Every
-// argument is wave-uniform.
-template <int R, int K, int M, bool ALIGNED>
+// argument is wave-uniform.  EDGE = false is the interior form: the strip's
+// columns and every row its stages touch lie inside the grid
+// (star2d_interior), so no clamp is ever applied and the border code is
+// left out; for such a strip it computes the same bits as the general form.
+template <int R, int K, int M, bool ALIGNED, bool EDGE = true>
 __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float *__restrict__ dst,
                                             int nx, int ny, int ly, int strip, int seg,
                                             const Coefs &cf) {
@@ -95,6 +107,7 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
     // Clamp in x: cells left of column 0 take column 0, cells right of
     // column nx-1 take column nx-1 (of the same row and stage).
     auto xfix = [&](float (&v)[VEC]) STAR_INLINE {
+        if constexpr (!EDGE) return;
         if (left_edge) {
             const int l0 = (-xs) / VEC;  // lane whose element 0 is column 0
             const float b = lane_value(v[0], l0);
@@ -120,14 +133,14 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
     // as the last row.  The x-clamp of a loaded row is applied when the row
     // enters stage 1 (consume_row), so no load is waited for early.
     auto load_row = [&](int j, float (&v)[VEC]) STAR_INLINE {
-        const float *row = src + (size_t)clampi(min(j, jlast), ny) * (size_t)nx;
+        const float *row = src + (size_t)(EDGE ? clampi(min(j, jlast), ny) : min(j, jlast)) * (size_t)nx;
         if constexpr (ALIGNED) {
-            const int c = min(max(col0, 0), nx - VEC);
+            const int c = EDGE ? min(max(col0, 0), nx - VEC) : col0;
             const float4 t = *reinterpret_cast<const float4 *>(row + c);
             v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
         } else {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) v[e] = row[clampi(col0 + e, nx)];
+            for (int e = 0; e < VEC; ++e) v[e] = row[EDGE ? clampi(col0 + e, nx) : col0 + e];
         }
     };
 
@@ -164,25 +177,29 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
             const int r = j - S * R;  // row produced by stage S
             float res[VEC];
             if constexpr (S == 1)
-                star2d_row<R, NQ, (PH - R + NQ) % NQ>(q0, cf, res);
+                star2d_row<R, NQ, (PH - R + NQ) % NQ, EDGE>(q0, cf, res);
             else
-                star2d_row<R, P, (PH % P - R + P) % P>(q[S - 2], cf, res);
+                star2d_row<R, P, (PH % P - R + P) % P, EDGE>(q[S - 2], cf, res);
             if constexpr (S < K) {
                 constexpr int W = PH % P;  // slot of this row in the stage's window
-                if (r >= ny) {
+                if constexpr (EDGE) {
+                    if (r >= ny) {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(W + P - 1) % P][e];
-                } else {
-                    xfix(res);
+                        for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(W + P - 1) % P][e];
+                    } else {
+                        xfix(res);
+                    }
                 }
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) q[S - 1][W][e] = res[e];
-                if (r == 0) {
-                    static_for<1, R + 1>([&](auto mc) STAR_INLINE {
-                        constexpr int MM = decltype(mc)::value;
+                if constexpr (EDGE) {
+                    if (r == 0) {
+                        static_for<1, R + 1>([&](auto mc) STAR_INLINE {
+                            constexpr int MM = decltype(mc)::value;
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) q[S - 1][(W - MM + P) % P][e] = res[e];
-                    });
+                            for (int e = 0; e < VEC; ++e) q[S - 1][(W - MM + P) % P][e] = res[e];
+                        });
+                    }
                 }
             } else {
                 // Stage K: write row r.  The store is issued on every row;
@@ -212,6 +229,17 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
     static_for<0, NQ>([&](auto phc) STAR_INLINE {
         if (n0 + decltype(phc)::value < niter) step_row(phc, n0 + decltype(phc)::value);
     });
+}
+
+// True when strip `strip` of segment `seg` needs no clamp at any stage: its
+// 64*VEC columns lie inside the grid, and rows y0-2KR .. y1-1+KR (the rows
+// its stages read and produce) do too.
+template <int R, int K>
+__device__ __forceinline__ bool star2d_interior(int nx, int ny, int ly, int strip, int seg) {
+    const int xs = strip * star2d_tile_x(K, R) - star2d_halo(K, R);
+    const int y0 = seg * ly;
+    const int y1 = min(y0 + ly, ny);
+    return xs >= 0 && xs + 64 * VEC <= nx && y0 > 2 * K * R && y1 + K * R <= ny;
 }
 
 // Input-ring multiple: deeper prefetch for the memory-bound small-K passes.
