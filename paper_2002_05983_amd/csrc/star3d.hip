@@ -20,8 +20,14 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
                                                       int nz, int hx, int tx, int ntx, int nty,
                                                       int lz, Coefs cf) {
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    star3d_body<R, K, VEC, WL, D, ALIGNED>(src, dst, nx, ny, nz, hx, tx, lb % ntx,
-                                           (lb / ntx) % nty, lb / (ntx * nty), lz, cf);
+    const int strip = lb % ntx, ytile = (lb / ntx) % nty, zseg = lb / (ntx * nty);
+    const int nt = (blockDim.x >> 6) * (64 / WL);
+    if (s3d::star3d_interior<R, K, VEC, WL>(nx, ny, nz, hx, tx, strip, ytile, zseg, lz, nt))
+        star3d_body<R, K, VEC, WL, D, ALIGNED, false>(src, dst, nx, ny, nz, hx, tx, strip, ytile,
+                                                      zseg, lz, cf);
+    else
+        star3d_body<R, K, VEC, WL, D, ALIGNED, true>(src, dst, nx, ny, nz, hx, tx, strip, ytile,
+                                                     zseg, lz, cf);
 }
 
 template <int K, int VEC, int WL, bool AL>

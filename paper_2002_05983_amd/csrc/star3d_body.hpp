@@ -62,8 +62,11 @@ __device__ __forceinline__ void lds_read_row(const float *row, int lr, float (&v
 
 // One workgroup's work: x-strip `strip`, tile row band `ytile` and
 // z-segment `zseg` of one grid (all block-uniform).  Uses the dynamic LDS
-// and one barrier per plane.
-template <int R, int K, int VEC, int WL, int D, bool ALIGNED>
+// and one barrier per plane.  EDGE = false is the interior form for a tile
+// whose columns, rows and planes stay inside the grid at every stage
+// (star3d_interior): no clamp is ever applied and the border code is left
+// out; for such a tile it computes the same bits as the general form.
+template <int R, int K, int VEC, int WL, int D, bool ALIGNED, bool EDGE = true>
 __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float *__restrict__ dst,
                                             int nx, int ny, int nz, int hx, int tx, int strip,
                                             int ytile, int zseg, int lz, const Coefs &cf) {
@@ -112,7 +115,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     };
     // Tile row holding grid row clamp(yy) (clamped into the tile as well).
     auto tile_row = [&](int yy) STAR_INLINE -> int {
-        const int r = clampi(yy, ny) - (ty0 - K * R);
+        const int r = (EDGE ? clampi(yy, ny) : yy) - (ty0 - K * R);
         return r < 0 ? 0 : (r >= nt ? nt - 1 : r);
     };
     // Value of v in lane `l` of this lane's tile row.
@@ -124,6 +127,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     };
 
     auto xfix = [&](float (&v)[VEC]) STAR_INLINE {
+        if constexpr (!EDGE) return;
         if (left_edge) {
             const int l0 = (-xs) / VEC;
             const float b = row_value(v[0], l0);
@@ -145,17 +149,18 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     };
 
     auto load_plane = [&](int zz, float (&v)[VEC]) STAR_INLINE {
-        const float *row = src + (size_t)clampi(min(zz, zlast), nz) * plane + (size_t)yc * nx;
+        const float *row =
+            src + (size_t)(EDGE ? clampi(min(zz, zlast), nz) : min(zz, zlast)) * plane + (size_t)yc * nx;
         if constexpr (ALIGNED) {
 #pragma unroll
             for (int c = 0; c < VEC / 4; ++c) {
-                const int cc = min(max(col0 + 4 * c, 0), nx - 4);
+                const int cc = EDGE ? min(max(col0 + 4 * c, 0), nx - 4) : col0 + 4 * c;
                 const float4 t = *reinterpret_cast<const float4 *>(row + cc);
                 v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) v[e] = row[clampi(col0 + e, nx)];
+            for (int e = 0; e < VEC; ++e) v[e] = row[EDGE ? clampi(col0 + e, nx) : col0 + e];
         }
     };
 
@@ -168,8 +173,13 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
         float left[R + 1], right[R + 1];
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
-            left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);
-            right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);
+            if constexpr (EDGE) {
+                left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);
+                right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);
+            } else {  // the wavefront's end lanes hold halo columns
+                left[k] = from_lower_lane_or_zero(q[CS][VEC - k]);
+                right[k] = from_upper_lane_or_zero(q[CS][k - 1]);
+            }
         }
         float acc[VEC];
 #pragma unroll
@@ -245,20 +255,24 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
                           res);
                 if constexpr (S < K) {
                     constexpr int WS = PS;
-                    if (r >= nz) {
+                    if constexpr (EDGE) {
+                        if (r >= nz) {
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(WS + P - 1) % P][e];
-                    } else {
-                        xfix(res);
+                            for (int e = 0; e < VEC; ++e) res[e] = q[S - 1][(WS + P - 1) % P][e];
+                        } else {
+                            xfix(res);
+                        }
                     }
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) q[S - 1][WS][e] = res[e];
-                    if (r == 0) {
-                        static_for<1, R + 1>([&](auto mc) STAR_INLINE {
-                            constexpr int MM = decltype(mc)::value;
+                    if constexpr (EDGE) {
+                        if (r == 0) {
+                            static_for<1, R + 1>([&](auto mc) STAR_INLINE {
+                                constexpr int MM = decltype(mc)::value;
 #pragma unroll
-                            for (int e = 0; e < VEC; ++e) q[S - 1][(WS - MM + P) % P][e] = res[e];
-                        });
+                                for (int e = 0; e < VEC; ++e) q[S - 1][(WS - MM + P) % P][e] = res[e];
+                            });
+                        }
                     }
                 } else {
                     // one descriptor per plane (wave-uniform); the row goes
@@ -294,6 +308,21 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     static_for<0, U>([&](auto phc) STAR_INLINE {
         if (n0 + decltype(phc)::value < niter) step_plane(phc, n0 + decltype(phc)::value);
     });
+}
+
+// True when a tile needs no clamp at any stage: its columns xs .. xs+W-1,
+// its rows ty0-KR .. ty0-KR+nt-1 and the planes z0-2KR .. z1-1+KR its
+// stages read and produce all lie inside the grid.
+template <int R, int K, int VEC, int WL>
+__device__ __forceinline__ bool star3d_interior(int nx, int ny, int nz, int hx, int tx, int strip,
+                                                int ytile, int zseg, int lz, int nt) {
+    const int xs = strip * tx - hx;
+    const int ty = nt - 2 * K * R;
+    const int y0 = ytile * ty - K * R;
+    const int z0 = zseg * lz;
+    const int z1 = min(z0 + lz, nz);
+    return hx > 0 && xs >= 0 && xs + WL * VEC <= nx && y0 >= 0 && y0 + nt <= ny &&
+           z0 > 2 * K * R && z1 + K * R <= nz;
 }
 
 // Prefetch depth (planes) per configuration, sized so that a 1024-thread
