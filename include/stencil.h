@@ -143,8 +143,8 @@ STENCIL_API int stencil_run_batched(int n, const stencil_plan_t *plans, const fl
 /*
  * The batched form as a reusable object.  Not in the paper, which runs one
  * grid at a time; this is the many-grids form of the same method: grids are
- * grouped into classes (dimension, radius, row alignment, size: 2D grids of
- * >= 2^18 cells and 3D grids of >= 2^20 cells are "large"); each class has
+ * grouped into classes (dimension, radius, size: 2D grids of >= 2^18 cells
+ * and 3D grids of >= 2^20 cells are "large"); each class has
  * one kernel configuration and runs as a chain of pass rounds (K fused steps
  * per round, a grid's last pass taking the remainder), each round one
  * launch of a persistent work-list kernel whose workgroups take
@@ -160,7 +160,9 @@ STENCIL_API int stencil_run_batched(int n, const stencil_plan_t *plans, const fl
  *         K, vec=8 applies only to aligned single-step R <= 2 classes with
  *         wl=64 -- "streams=" (side streams, 1..16, default 4) and "graph="
  *         (1 = replay the captured graph, the default; 0 = enqueue the
- *         launches on every call).  Without overrides a class takes its
+ *         launches on every call) and "merge=0" (row-aligned grids keep
+ *         classes of their own; by default they join the unaligned class
+ *         of their kind: fewer, fuller pass rounds).  Without overrides a class takes its
  *         configuration from the tuning cache, else built-in defaults.
  *   Grids with steps == 0, low-precision storage, or 3D planes of 2^31
  *   bytes or more are run by their own plan inside the batch.

@@ -50,7 +50,18 @@ def _obj_name(src: str, defs: dict) -> str:
     return f"{stem}{suffix}.o"
 
 
-def build(verbose: bool = False, asm_dir: str | None = None, jobs: int | None = None) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """An object is stale when older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    headers += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+    return any(os.path.getmtime(f) > t for f in [src] + headers)
+
+
+def build(verbose: bool = False, asm_dir: str | None = None, jobs: int | None = None,
+          incremental: bool = False) -> str:
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -68,6 +79,8 @@ def build(verbose: bool = False, asm_dir: str | None = None, jobs: int | None = 
         cmds.append(cmd)
 
     def run(cmd):
+        if incremental and "-c" in cmd and not _stale(cmd[-1], cmd[cmd.index("-c") + 1]):
+            return cmd[-1]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -96,5 +109,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--asm", default=None, help="copy the gfx950 assembly of each unit here")
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only units older than their source or a header")
     args = ap.parse_args()
-    print(build(verbose=args.verbose, asm_dir=args.asm))
+    print(build(verbose=args.verbose, asm_dir=args.asm, incremental=args.incremental))

@@ -33,12 +33,12 @@ constexpr double kCyclesPerWaveInstr = 4.0;  // wave64 on a 16-lane SIMD
 // Fitted to the autotuner's measurements on MI355X (every candidate of 13
 // problems: 2D 16384^2 and 4096^2, 3D 512^3, 768^3 and 192x256x320) by a
 // grid search minimising mean |log(predicted / measured)|:
-constexpr double kHbmEff = 5.0e12;           // B/s reached by the streaming passes
-constexpr double kLaunch2D = 12e-6, kLaunch3D = 4e-6;  // s per pass launch
+constexpr double kHbmEff2D = 5.0e12, kHbmEff3D = 4.5e12;  // B/s reached by the passes
+constexpr double kLaunch2D = 20e-6, kLaunch3D = 2e-6;      // s per pass launch
 // instructions per wavefront row and stage beyond the FMAs and lane shifts
 // (clamps, register moves, index arithmetic), and per streamed row
-constexpr double kRowStage2D = 15.0, kRow2D = 40.0;
-constexpr double kRowStage3D = 30.0, kRow3D = 12.0, kLoadOnly3D = 20.0;
+constexpr double kRowStage2D = 12.5, kRow2D = 32.0;
+constexpr double kRowStage3D = 25.0, kRow3D = 24.0, kLoadOnly3D = 20.0;
 // per-plane critical path of a 3D workgroup beyond its VALU issue time
 // (LDS write, barrier, LDS reads), cycles
 constexpr double kPlaneLatency3D = 400.0;
@@ -64,7 +64,7 @@ Pass model_2d(const stencil_plan_s *p, int K) {
     // wind-up rows are re-read from HBM; the overlapped halo columns of
     // neighbouring strips mostly come from L2
     const double cells = nx * ny;
-    s.t_hbm = (cells * 4.0 * (rows / ly) + cells * 4.0) / kHbmEff;
+    s.t_hbm = (cells * 4.0 * (rows / ly) + cells * 4.0) / kHbmEff2D;
     return s;
 }
 
@@ -102,7 +102,7 @@ Pass model_3d(const stencil_plan_s *p, int K) {
     const double rounds = std::ceil(blocks / kCUs);
     s.t_plane = rounds * planes * plane_cycles / kClock;
     const double cells = nx * ny * nz;
-    s.t_hbm = (cells * 4.0 * (planes / lz) * (nt / ty) + cells * 4.0) / kHbmEff;
+    s.t_hbm = (cells * 4.0 * (planes / lz) * (nt / ty) + cells * 4.0) / kHbmEff3D;
     return s;
 }
 

@@ -47,7 +47,8 @@ TUNES = [
     "2d.k=1,3d.k=1",
     "2d.k=3,2d.ly=16,3d.k=2,3d.lz=8",
     "2d.k=8,2d.ly=256,3d.wl=64,3d.nw=12,3d.lz=32",
-    "3d.vec=8,3d.wl=64,3d.k=1,streams=1",
+    "3d.vec=8,3d.wl=64,3d.k=1,streams=1,merge=0",
+    "merge=0,2d.k=2",
     "graph=0,streams=2",
     "streams=16,3d.nw=8",
 ]
