@@ -49,7 +49,11 @@ def lib() -> ctypes.CDLL:
         L.oracle_star_sample_f64.argtypes = [ctypes.c_int, i64p, ctypes.c_int, dp, ctypes.c_int,
                                              fp, ctypes.c_int64, i64p, ctypes.c_int64, dp,
                                              ctypes.c_int]
-        for f in (L.oracle_star_run_f64, L.oracle_star_run_f32, L.oracle_star_sample_f64):
+        L.oracle_star_sample_f32.argtypes = [ctypes.c_int, i64p, ctypes.c_int, fp, ctypes.c_int,
+                                             fp, ctypes.c_int64, i64p, ctypes.c_int64, fp,
+                                             ctypes.c_int]
+        for f in (L.oracle_star_run_f64, L.oracle_star_run_f32, L.oracle_star_sample_f64,
+                  L.oracle_star_sample_f32):
             f.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -133,6 +137,30 @@ def star_sample_f64(f0: np.ndarray, coeffs, radius: int, steps: int, cells,
                                       _ptr(tri, ctypes.c_int64), int(cl.shape[0]),
                                       _ptr(vals, ctypes.c_double), int(threads or max_threads()))
     _check(rc, "star_sample_f64")
+    return vals
+
+
+def star_sample_f32(f0: np.ndarray, coeffs, radius: int, steps: int, cells,
+                    threads: int = 0) -> np.ndarray:
+    """f^steps at the given cells in the FP32 order of star_run_f32, each
+    from its own dependence cone (bitwise the full-grid FP32 values).
+
+    cells: integer array (n, ndim) of coordinates in x, y[, z] order.
+    """
+    f = np.ascontiguousarray(f0, dtype=np.float32)
+    c = np.ascontiguousarray(np.asarray(coeffs), dtype=np.float32)
+    cl = np.asarray(cells, dtype=np.int64)
+    tri = np.zeros((cl.shape[0], 3), dtype=np.int64)
+    tri[:, :cl.shape[1]] = cl
+    tri = np.ascontiguousarray(tri)
+    vals = np.empty(cl.shape[0], dtype=np.float32)
+    dims = _dims_xyz(f.shape)
+    rc = lib().oracle_star_sample_f32(f.ndim, _ptr(dims, ctypes.c_int64), int(radius),
+                                      _ptr(c, ctypes.c_float), int(c.size),
+                                      _ptr(f, ctypes.c_float), int(steps),
+                                      _ptr(tri, ctypes.c_int64), int(cl.shape[0]),
+                                      _ptr(vals, ctypes.c_float), int(threads or max_threads()))
+    _check(rc, "star_sample_f32")
     return vals
 
 

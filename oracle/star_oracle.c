@@ -261,6 +261,83 @@ int oracle_star_sample_f64(int ndim, const int64_t *dims, int rad,
     return status;
 }
 
+/*
+ * Single-precision counterpart of oracle_star_sample_f64: f^steps at the
+ * given cells, each from its own dependence cone, with the operations and
+ * order of oracle_star_run_f32 (so every sampled value equals the one the
+ * full-grid single-precision run gives, bit for bit).
+ */
+int oracle_star_sample_f32(int ndim, const int64_t *dims, int rad,
+                           const float *coef, int ncoef,
+                           const float *f0, int64_t steps,
+                           const int64_t *cells, int64_t ncells,
+                           float *vals, int nthreads)
+{
+    int64_t nx, ny, nz;
+    if (check_args(ndim, dims, rad, ncoef, steps, &nx, &ny, &nz)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    int status = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int64_t q = 0; q < ncells; ++q) {
+        int64_t p[3] = {cells[3 * q], cells[3 * q + 1], ndim == 3 ? cells[3 * q + 2] : 0};
+        int64_t n3[3] = {nx, ny, nz};
+        int64_t lo[3], hi[3], ext[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t reach = (a < ndim) ? steps * (int64_t)rad : 0;
+            lo[a] = p[a] - reach < 0 ? 0 : p[a] - reach;
+            hi[a] = p[a] + reach + 1 > n3[a] ? n3[a] : p[a] + reach + 1;
+            ext[a] = hi[a] - lo[a];
+        }
+        size_t m = (size_t)ext[0] * ext[1] * ext[2];
+        float *a = (float *)malloc(m * sizeof(float));
+        float *b = (float *)malloc(m * sizeof(float));
+        if (!a || !b) {
+            free(a); free(b);
+#pragma omp atomic write
+            status = -2;
+            continue;
+        }
+        for (int64_t z = 0; z < ext[2]; ++z)
+            for (int64_t y = 0; y < ext[1]; ++y)
+                for (int64_t x = 0; x < ext[0]; ++x)
+                    a[x + ext[0] * (y + ext[1] * z)] =
+                        f0[(lo[0] + x) + nx * ((lo[1] + y) + ny * (lo[2] + z))];
+        for (int64_t t = 0; t < steps; ++t) {
+            int64_t keep = (steps - t - 1) * (int64_t)rad;
+            int64_t l2[3], h2[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                int64_t r = (ax < ndim) ? keep : 0;
+                l2[ax] = p[ax] - r < lo[ax] ? lo[ax] : p[ax] - r;
+                h2[ax] = p[ax] + r + 1 > hi[ax] ? hi[ax] : p[ax] + r + 1;
+            }
+            for (int64_t z = l2[2]; z < h2[2]; ++z)
+                for (int64_t y = l2[1]; y < h2[1]; ++y)
+                    for (int64_t x = l2[0]; x < h2[0]; ++x) {
+#define G(xx, yy, zz) a[((xx) - lo[0]) + ext[0] * (((yy) - lo[1]) + ext[1] * ((zz) - lo[2]))]
+                        float acc = coef[0] * G(x, y, z);
+                        int k = 1;
+                        for (int i = 1; i <= rad; ++i) {
+                            acc = fmaf(coef[k], G(clamp_index(x - i, nx), y, z), acc); ++k;
+                            acc = fmaf(coef[k], G(clamp_index(x + i, nx), y, z), acc); ++k;
+                            acc = fmaf(coef[k], G(x, clamp_index(y - i, ny), z), acc); ++k;
+                            acc = fmaf(coef[k], G(x, clamp_index(y + i, ny), z), acc); ++k;
+                            if (ndim == 3) {
+                                acc = fmaf(coef[k], G(x, y, clamp_index(z - i, nz)), acc); ++k;
+                                acc = fmaf(coef[k], G(x, y, clamp_index(z + i, nz)), acc); ++k;
+                            }
+                        }
+                        b[(x - lo[0]) + ext[0] * ((y - lo[1]) + ext[1] * (z - lo[2]))] = acc;
+#undef G
+                    }
+            float *tmp = a; a = b; b = tmp;
+        }
+        vals[q] = a[(p[0] - lo[0]) + ext[0] * ((p[1] - lo[1]) + ext[1] * (p[2] - lo[2]))];
+        free(a);
+        free(b);
+    }
+    return status;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -335,6 +335,10 @@ def test_sampled_cells_match_full_sweep(oracle_mod, shape, radius, steps):
     vals = oracle_mod.star_sample_f64(f, c, radius, steps, cells)
     want = np.array([full[tuple(p[::-1])] for p in cells])
     np.testing.assert_array_equal(vals, want)
+    # the single-precision cone evaluation equals the single-precision sweep
+    full32 = oracle_mod.star_run_f32(f, c, radius, steps)
+    vals32 = oracle_mod.star_sample_f32(f, c, radius, steps, cells)
+    np.testing.assert_array_equal(vals32, np.array([full32[tuple(p[::-1])] for p in cells]))
 
 
 def test_invalid_arguments(oracle_mod):
