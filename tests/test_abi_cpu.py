@@ -151,3 +151,11 @@ def test_tune_strings_are_validated_before_the_device(lib, ndim, dims, radius, t
             lib.stencil_plan_destroy(h)
     else:
         assert rc == -1, (rc, lib.stencil_last_error())
+
+
+def test_3d_plane_limit_is_checked_before_the_device(lib):
+    # 8 x 67108864 cells x 4 B = 2^31 bytes per plane: beyond 32-bit plane offsets
+    c = [0.1] * 7
+    rc, h = _plan(lib, 3, [67108864, 8, 2], 1, c)
+    assert rc == -4 and not h.value, (rc, lib.stencil_last_error())
+    assert b"2^31" in lib.stencil_last_error()
