@@ -7,11 +7,12 @@ each radius with its plan's temporal degree K.  Inputs are resident in HBM
 before timing starts.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-tune] [--no-3d]
+                  [--no-high] [--no-precision] [--no-batch]
 
 Each plan is autotuned (every feasible kernel configuration timed at the
 real shape) before the timed region.  Secondary legs, reported under
-"extra": the 3D workload (512^3, radius 1..4, 200 steps each) measured the
-same way; the precision form (768^3 radius 4, 1000 steps, FP32 against
+"extra": 2D radius 5..8 on the same grid (200 steps each); the 3D workload
+(512^3, radius 1..4, 200 steps each) measured the same way; the precision form (768^3 radius 4, 1000 steps, FP32 against
 FP16/BF16 storage re-anchored every 10 or 50 steps, with errors); and the
 batched form (256 mixed 2D/3D grids, 100 steps, one captured batch against
 256 single-grid runs).
@@ -167,6 +168,41 @@ def bench_3d(stencil, synth, torch, dev, side=512, time_steps=200, reps=2, tune=
     total = x.numel() * time_steps * len(RADII) / (tot_ms / 1e3) / 1e9
     return {"workload": f"3D star stencils r=1..4, {side}^3 FP32 U[0,1), {time_steps} steps per "
                         f"radius, clamp", "GCell/s": round(total, 1), "per_radius": rows}
+
+
+def bench_2d_high(stencil, synth, torch, dev, side=SIDE, time_steps=200, reps=2, tune=True):
+    """2D star stencils r=5..8 on side^2 FP32 (U[0,1)), time_steps steps each:
+    the radii past the paper's four, where it expects temporal blocking to
+    keep paying off in 2D (Sec. VI.A)."""
+    shape = (side, side)
+    x = torch.from_numpy(synth.grid_uniform(1, shape)).to(dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    rows, tot_ms = [], 0.0
+    radii = (5, 6, 7, 8)
+    for r in radii:
+        p = stencil.Plan(shape, r, synth.coefficients(1000 + r, 2, r))
+        if tune:
+            p.autotune(x, y, stream=stream)
+        p.run(x, y, time_steps, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(stream)
+        for _ in range(reps):
+            p.run(x, y, time_steps, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b) / reps
+        tot_ms += ms
+        gc = x.numel() * time_steps / (ms / 1e3) / 1e9
+        rows.append({"radius": r, "K": p.query()["K"], "ms": round(ms, 3), "GCell/s": round(gc, 1),
+                     "GFLOP/s": round(gc * flop_per_cell(2, r), 1),
+                     "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
+                     "config": p.describe()})
+        p.close()
+    total = x.numel() * time_steps * len(radii) / (tot_ms / 1e3) / 1e9
+    return {"workload": f"2D star stencils r=5..8, {side}x{side} FP32 U[0,1), {time_steps} steps "
+                        f"per radius, clamp", "GCell/s": round(total, 1), "per_radius": rows}
 
 
 def read_precision_reference():
@@ -328,6 +364,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the secondary 3D leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-high", action="store_true", help="skip the 2D radius 5..8 leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
     ap.add_argument("--time-steps", type=int, default=TIME_STEPS, help=argparse.SUPPRESS)
     ap.add_argument("--config", action="append", default=[], metavar="R:TUNE", help=argparse.SUPPRESS)
@@ -468,6 +505,10 @@ def main():
     torch.cuda.empty_cache()
     progress(f"2D: {value:.1f} GCell/s")
     extra = {}
+    if not args.no_high:
+        extra["2d_high_radius"] = bench_2d_high(stencil, synth, torch, dev, side=side,
+                                                tune=not args.no_tune)
+        progress(f"2D r=5..8: {extra['2d_high_radius']['GCell/s']} GCell/s")
     if not args.no_3d:
         extra["3d"] = bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)
         progress(f"3D: {extra['3d']['GCell/s']} GCell/s")

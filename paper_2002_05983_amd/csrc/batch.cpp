@@ -685,7 +685,8 @@ int batch_create(stencil_batch_t *out, int n, const stencil_plan_t *plans, const
     for (int g = 0; g < n; ++g) {
         const stencil_plan_s *p = plans[g];
         const bool wide_plane = p->ndim == 3 && p->nx * p->ny * 4 >= ((int64_t)1 << 31);
-        if (steps[g] == 0 || p->storage != STENCIL_F32 || wide_plane) {
+        const bool high_radius = p->radius > 4;  // work-list kernels are built for R <= 4
+        if (steps[g] == 0 || p->storage != STENCIL_F32 || wide_plane || high_radius) {
             b->own.push_back(g);
             continue;
         }

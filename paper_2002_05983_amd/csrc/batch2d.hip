@@ -1,6 +1,6 @@
 // batch2d.hip -- persistent work-list kernel of the batched form, 2D grids.
 //
-// Compiled once per radius with -DSTAR_R=<1..4>.  Each wavefront takes one
+// Compiled once per radius with -DSTAR_R=<1..8>.  Each wavefront takes one
 // item (an x-strip and y-segment of one grid) at a time from the round's
 // atomic counter and runs the same per-wavefront body as the single-grid
 // kernel on it; wavefronts are independent (no barriers), so a workgroup's
@@ -16,10 +16,10 @@ namespace star {
 
 namespace {
 
-using s2d::ring_mult;
+using s2d::prefetch_rows;
 using s2d::star2d_body;
 
-template <int R, int K, int M, bool ALIGNED>
+template <int R, int K, int D, bool ALIGNED>
 __global__ __launch_bounds__(256) void star2d_batch(const BatchEntry *__restrict__ entries,
                                                     const BatchGrid *__restrict__ grids,
                                                     unsigned *counter, int nentries, int nitems) {
@@ -34,13 +34,13 @@ __global__ __launch_bounds__(256) void star2d_batch(const BatchEntry *__restrict
         const BatchGrid &g = grids[en.grid];
         const int t = item - en.item0;
         const Coefs cf = g.cf;
-        star2d_body<R, K, M, ALIGNED>(en.src, en.dst, g.nx, g.ny, g.seg, t % en.ntx, t / en.ntx, cf);
+        star2d_body<R, K, D, ALIGNED>(en.src, en.dst, g.nx, g.ny, g.seg, t % en.ntx, t / en.ntx, cf);
     }
 }
 
 template <int K, bool AL>
 const void *kernel_of() {
-    return (const void *)star2d_batch<STAR_R, K, ring_mult<STAR_R, K>(), AL>;
+    return (const void *)star2d_batch<STAR_R, K, prefetch_rows<STAR_R, K>(), AL>;
 }
 
 template <int K>

@@ -23,7 +23,7 @@ struct Star2DArgs {
 };
 constexpr int kMaxK2D = 8;
 // Largest K built per radius: K*R <= 16 keeps the unrolled queue code and
-// its registers in budget (K = 8, 8, 5, 4 for R = 1..4).
+// its registers in budget (K = 8, 8, 5, 4, 3, 2, 2, 2 for R = 1..8).
 constexpr int max_k2d(int R) { return 16 / R < kMaxK2D ? 16 / R : kMaxK2D; }
 constexpr int kVec2D = 4;
 // Output columns of one strip: a wavefront spans 64*4 columns, minus the
@@ -35,6 +35,10 @@ hipError_t launch_star2d_r1(const Star2DArgs &a, hipStream_t stream);
 hipError_t launch_star2d_r2(const Star2DArgs &a, hipStream_t stream);
 hipError_t launch_star2d_r3(const Star2DArgs &a, hipStream_t stream);
 hipError_t launch_star2d_r4(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r5(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r6(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r7(const Star2DArgs &a, hipStream_t stream);
+hipError_t launch_star2d_r8(const Star2DArgs &a, hipStream_t stream);
 
 // 3D xy-tile / z-stream kernel fusing K steps per pass.
 struct Star3DArgs {

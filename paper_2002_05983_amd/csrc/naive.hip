@@ -52,7 +52,7 @@ hipError_t launch_naive(int ndim, int R, const float *src, float *dst, int nx, i
     if (ndim == 2) nz = 1;
 #define CASE(ND, RR) \
     if (ndim == ND && R == RR) return launch_one<ND, RR>(src, dst, nx, ny, nz, cf, stream);
-    CASE(2, 1) CASE(2, 2) CASE(2, 3) CASE(2, 4)
+    CASE(2, 1) CASE(2, 2) CASE(2, 3) CASE(2, 4) CASE(2, 5) CASE(2, 6) CASE(2, 7) CASE(2, 8)
     CASE(3, 1) CASE(3, 2) CASE(3, 3) CASE(3, 4)
 #undef CASE
     return hipErrorInvalidValue;

@@ -23,7 +23,8 @@ int default_k2d(int R) {
         case 1: return 8;
         case 2: return 5;
         case 3: return 4;
-        default: return 4;
+        case 4: return 4;
+        default: return max_k2d(R);
     }
 }
 
@@ -236,6 +237,10 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
                 case 2: return launch_star2d_r2(a, stream);
                 case 3: return launch_star2d_r3(a, stream);
                 case 4: return launch_star2d_r4(a, stream);
+                case 5: return launch_star2d_r5(a, stream);
+                case 6: return launch_star2d_r6(a, stream);
+                case 7: return launch_star2d_r7(a, stream);
+                case 8: return launch_star2d_r8(a, stream);
             }
             return hipErrorInvalidValue;
         }

@@ -1,6 +1,6 @@
 // star2d.hip -- single-grid launch of the 2D star stencil (method in star2d_body.hpp).
 //
-// Compiled once per radius with -DSTAR_R=<1..4>.
+// Compiled once per radius with -DSTAR_R=<1..8>.
 #include "star2d_body.hpp"
 
 #ifndef STAR_R
@@ -11,10 +11,10 @@ namespace star {
 
 namespace {
 
-using s2d::ring_mult;
+using s2d::prefetch_rows;
 using s2d::star2d_body;
 
-template <int R, int K, int M, bool ALIGNED>
+template <int R, int K, int D, bool ALIGNED>
 __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ src,
                                                      float *__restrict__ dst, int nx, int ny,
                                                      int ly, int nstrips, int nwaves, Coefs cf) {
@@ -26,9 +26,9 @@ __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ s
     if (wave >= nwaves) return;
     const int strip = wave % nstrips, seg = wave / nstrips;
     if (s2d::star2d_interior<R, K>(nx, ny, ly, strip, seg))
-        star2d_body<R, K, M, ALIGNED, false>(src, dst, nx, ny, ly, strip, seg, cf);
+        star2d_body<R, K, D, ALIGNED, false>(src, dst, nx, ny, ly, strip, seg, cf);
     else
-        star2d_body<R, K, M, ALIGNED, true>(src, dst, nx, ny, ly, strip, seg, cf);
+        star2d_body<R, K, D, ALIGNED, true>(src, dst, nx, ny, ly, strip, seg, cf);
 }
 
 template <int K, bool AL>
@@ -39,7 +39,7 @@ hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
     const int64_t nwaves = (int64_t)nstrips * nsegs;
     if (nwaves > (int64_t)1 << 30) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    hipLaunchKernelGGL((star2d_stream<STAR_R, K, ring_mult<STAR_R, K>(), AL>), dim3(blocks), dim3(256), 0, stream, a.src,
+    hipLaunchKernelGGL((star2d_stream<STAR_R, K, prefetch_rows<STAR_R, K>(), AL>), dim3(blocks), dim3(256), 0, stream, a.src,
                        a.dst, a.nx, a.ny, a.ly, nstrips, (int)nwaves, a.cf);
     return hipGetLastError();
 }

@@ -46,15 +46,23 @@ constexpr int VEC = kVec2D;
 template <int R, int NS, int CS, bool EDGE>
 __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
                                            float (&res)[VEC]) {
+    static_assert(R <= 2 * VEC, "x-neighbours come from the lanes at most two away");
+    auto lower = [&](float v) STAR_INLINE {
+        return EDGE ? from_lower_lane(v, q[CS][0]) : from_lower_lane_or_zero(v);
+    };
+    auto upper = [&](float v) STAR_INLINE {
+        return EDGE ? from_upper_lane(v, q[CS][VEC - 1]) : from_upper_lane_or_zero(v);
+    };
+    // left[k]: column base - k; right[k]: column base + VEC - 1 + k
     float left[R + 1], right[R + 1];
 #pragma unroll
     for (int k = 1; k <= R; ++k) {
-        if constexpr (EDGE) {
-            left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);      // column base - k
-            right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);  // column base + VEC - 1 + k
-        } else {
-            left[k] = from_lower_lane_or_zero(q[CS][VEC - k]);
-            right[k] = from_upper_lane_or_zero(q[CS][k - 1]);
+        if (k <= VEC) {  // the adjacent lane
+            left[k] = lower(q[CS][VEC - k]);
+            right[k] = upper(q[CS][k - 1]);
+        } else {  // two lanes away
+            left[k] = lower(lower(q[CS][2 * VEC - k]));
+            right[k] = upper(upper(q[CS][k - VEC - 1]));
         }
     }
 #pragma unroll
@@ -81,15 +89,17 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
 // columns and every row its stages touch lie inside the grid
 // (star2d_interior), so no clamp is ever applied and the border code is
 // left out; for such a strip it computes the same bits as the general form.
-template <int R, int K, int M, bool ALIGNED, bool EDGE = true>
+template <int R, int K, int D, bool ALIGNED, bool EDGE = true>
 __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float *__restrict__ dst,
                                             int nx, int ny, int ly, int strip, int seg,
                                             const Coefs &cf) {
     constexpr int P = 2 * R + 1;  // rows a stage keeps: its y-window
-    constexpr int NQ = M * P;     // input ring: y-window plus (M-1)*P rows in flight
+    constexpr int NQ = P + D;     // input ring: y-window plus D rows in flight
+    // stage s >= 2 keeps its window in slot (ring slot mod P), which follows
+    // the row index only when P divides the ring length
+    static_assert(K == 1 || D % P == 0, "prefetch distance must be a multiple of the y-window");
     constexpr int H = star2d_halo(K, R);
     constexpr int TX = star2d_tile_x(K, R);
-    static_assert(R <= VEC, "x-neighbours must come from the adjacent lane");
 
     const int lane = threadIdx.x & 63;
     const int xs = strip * TX - H;  // first column held by lane 0
@@ -159,7 +169,7 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
 #pragma unroll
         for (int e = 0; e < VEC; ++e) q0[p][e] = 0.0f;
 
-    constexpr int DIST = NQ - P;  // prefetch distance in rows
+    constexpr int DIST = D;  // prefetch distance in rows
     static_for<0, DIST>([&](auto phc) STAR_INLINE {
         constexpr int PH = decltype(phc)::value;
         load_row(jstart + PH, q0[PH]);
@@ -242,9 +252,13 @@ __device__ __forceinline__ bool star2d_interior(int nx, int ny, int ly, int stri
     return xs >= 0 && xs + 64 * VEC <= nx && y0 > 2 * K * R && y1 + K * R <= ny;
 }
 
-// Input-ring multiple: deeper prefetch for the memory-bound small-K passes.
+// Rows in flight per wavefront: two y-windows for the memory-bound small-K
+// passes, one otherwise, and 8 rows (8 KiB per wavefront) for single-step
+// passes of R >= 5, where a whole window would cost more registers than the
+// latency needs.  With K > 1 it must be a multiple of the window (the
+// stages' window slots are derived from the input-ring slot).
 template <int R, int K>
-constexpr int ring_mult() { return K * R <= 2 ? 3 : 2; }
+constexpr int prefetch_rows() { return K * R <= 2 ? 2 * (2 * R + 1) : (K == 1 && R >= 5) ? 8 : 2 * R + 1; }
 
 }  // namespace s2d
 }  // namespace star

@@ -70,7 +70,7 @@ def _plan(lib, ndim, dims, radius, coeffs, ncoeffs=None, boundary=0, storage=0, 
     dict(ndim=1, dims=[4], radius=1, coeffs=[0.0] * 3),
     dict(ndim=4, dims=[4] * 4, radius=1, coeffs=[0.0] * 9),
     dict(ndim=2, dims=[4, 4], radius=0, coeffs=[0.0]),
-    dict(ndim=2, dims=[4, 4], radius=5, coeffs=[0.0] * 21),
+    dict(ndim=2, dims=[4, 4], radius=9, coeffs=[0.0] * 37),
     dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 4),
     dict(ndim=3, dims=[4, 4, 4], radius=2, coeffs=[0.0] * 9),
     dict(ndim=2, dims=[0, 4], radius=1, coeffs=[0.0] * 5),
@@ -86,6 +86,15 @@ def test_plan_rejects_invalid_arguments(lib, case):
     assert rc == -1, (case, rc, lib.stencil_last_error())
     assert not h.value
     assert lib.stencil_last_error()
+
+
+def test_plan_radius_limits(lib):
+    """2D plans take radius 1..8; 3D kernels are built for radius 1..4, so a
+    3D radius of 5..8 is a valid request this build does not support."""
+    for radius in (5, 8):
+        rc, h = _plan(lib, 3, [16, 16, 16], radius, [0.0] * (1 + 6 * radius))
+        assert rc == -4 and not h.value, (radius, rc)
+        assert b"radius" in lib.stencil_last_error()
 
 
 def test_plan_null_out_pointer(lib):

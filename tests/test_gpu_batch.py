@@ -148,14 +148,15 @@ def test_batch_rejects_shared_memory_and_bad_tune(torch, st):
         st.Batch(p3, i3, o3, [-1])
 
 
-def test_batch_hands_lowp_and_zero_step_grids_to_their_plans(torch, st):
+def test_batch_hands_lowp_zero_step_and_high_radius_grids_to_their_plans(torch, st):
     f16 = synth.grid_uniform(7301, (9, 70, 72))
     c16 = synth.coefficients(7302, 3, 2)
     plan16 = st.Plan(f16.shape, 2, c16, storage="f16", anchor_m=3)
     x16 = torch.from_numpy(f16).cuda()
     ref16 = torch.empty_like(x16)
     plan16.run(x16, ref16, 7)
-    data = make_inputs([((50, 300), 3, 6), ((12, 30, 40), 1, 5), ((20, 20), 1, 0)], 7310)
+    data = make_inputs([((50, 300), 3, 6), ((12, 30, 40), 1, 5), ((20, 20), 1, 0),
+                        ((40, 600), 7, 5)], 7310)
     plans, ins, outs, steps = build(torch, st, data)
     refs = []
     for p, x, s in zip(plans, ins, steps):

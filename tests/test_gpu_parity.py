@@ -53,6 +53,7 @@ def assert_bitwise(got, want, what):
 
 
 NAIVE_CASES = [((1, 1), 1), ((3, 2), 4), ((17, 33), 2), ((64, 100), 3), ((5, 200), 4),
+               ((2, 3), 8), ((40, 70), 5), ((19, 260), 6), ((33, 17), 7),
                ((1, 1, 1), 2), ((4, 5, 6), 3), ((9, 17, 33), 1), ((3, 40, 7), 4)]
 
 
@@ -71,7 +72,7 @@ S2D_SHAPES = [(1, 1), (1, 7), (6, 1), (3, 3), (2, 5), (37, 513), (97, 1000), (13
               (64, 2048), (300, 260), (11, 4096)]
 
 
-@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("radius", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("shape", S2D_SHAPES)
 def test_s2d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
     c = synth.coefficients(400 + radius, 2, radius)
@@ -89,7 +90,7 @@ def test_s2d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
             assert_bitwise(got, cache[steps], f"s2d {shape} r{radius} k{K} ly{ly}")
 
 
-@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("radius", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_s2d_default_config_vs_fp64(torch, st, oracle_mod, radius):
     """Default (autoselected) configuration, 40 steps, against FP64."""
     shape = (257, 1531)

@@ -119,6 +119,30 @@ def test_brute_force_matrix_power(oracle_mod, radius, shape):
         np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-14)
 
 
+@pytest.mark.parametrize("radius", [5, 6, 7, 8])
+@pytest.mark.parametrize("shape", [(11, 9), (3, 12), (1, 10), (17, 2)])
+def test_high_radius_2d_pins(oracle_mod, radius, shape):
+    """2D radius 5..8: unit-coefficient shifts equal edge-padded shifts, and
+    oracle(f, s) equals A^s f, on grids whose sides are below, at and above
+    the radius."""
+    f = synth.grid_uniform(9, shape)
+    for i in (1, radius - 1, radius):
+        for d in DIRS[2]:
+            c = np.zeros(1 + 4 * radius, dtype=np.float32)
+            c[coef_index(2, d, i)] = 1.0
+            want = edge_shift(f.astype(np.float64), d, i)
+            np.testing.assert_array_equal(oracle_mod.star_run_f64(f, c, radius, 1), want)
+            np.testing.assert_array_equal(oracle_mod.star_run_f32(f, c, radius, 1),
+                                          want.astype(np.float32))
+    c = synth.coefficients(150 + radius, 2, radius).astype(np.float64)
+    A = dense_operator(shape, 2, radius, c)
+    g = f.astype(np.float64)
+    for s in (1, 3):
+        want = (np.linalg.matrix_power(A, s) @ g.ravel()).reshape(shape)
+        np.testing.assert_allclose(oracle_mod.star_run_f64(g, c, radius, s), want,
+                                   rtol=1e-13, atol=1e-14)
+
+
 @pytest.mark.parametrize("shape", [(13, 17), (6, 7, 9)])
 def test_linearity(oracle_mod, shape):
     ndim = len(shape)
