@@ -33,11 +33,12 @@ constexpr double kCyclesPerWaveInstr = 4.0;  // wave64 on a 16-lane SIMD
 // Fitted to the autotuner's measurements on MI355X (every candidate of 13
 // problems: 2D 16384^2 and 4096^2, 3D 512^3, 768^3 and 192x256x320) by a
 // grid search minimising mean |log(predicted / measured)|:
-constexpr double kHbmEff2D = 5.0e12, kHbmEff3D = 4.5e12;  // B/s reached by the passes
-constexpr double kLaunch2D = 20e-6, kLaunch3D = 2e-6;      // s per pass launch
+constexpr double kHbmEff2D = 5.0e12, kHbmEff3D = 5.0e12;  // B/s reached by the passes
+// s per pass: launch, plus (2D) the ramp-up and drain of the last wavefronts
+constexpr double kLaunch2D = 30e-6, kLaunch3D = 2e-6;
 // instructions per wavefront row and stage beyond the FMAs and lane shifts
 // (clamps, register moves, index arithmetic), and per streamed row
-constexpr double kRowStage2D = 12.5, kRow2D = 32.0;
+constexpr double kRowStage2D = 10.0, kRow2D = 16.0;
 constexpr double kRowStage3D = 25.0, kRow3D = 24.0, kLoadOnly3D = 20.0;
 // per-plane critical path of a 3D workgroup beyond its VALU issue time
 // (LDS write, barrier, LDS reads), cycles
@@ -54,13 +55,16 @@ Pass model_2d(const stencil_plan_s *p, int K) {
     const double ly = std::min<double>(p->ly, ny);
     const double nstrips = std::ceil(nx / TX), nsegs = std::ceil(ny / ly);
     const double rows = ly + 2.0 * K * R;  // streamed per wavefront
+    // stage s starts 2sR rows into the stream: sum over s of (rows - 2sR)
+    const double stage_rows = K * (ly + (K - 1.0) * R);
     const double waves = nstrips * nsegs;
-    const double per_row = K * (kVec2D * (4.0 * R + 1.0) + 2.0 * R + kRowStage2D) + kRow2D;
-    const double instr = waves * rows * per_row;
+    const double per_stage_row = kVec2D * (4.0 * R + 1.0) + 2.0 * R + kRowStage2D;
+    const double per_wave = rows * kRow2D + stage_rows * per_stage_row;
+    const double instr = waves * per_wave;
     Pass s;
     s.t_valu = instr * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
     // few wavefronts: each streams its rows alone on its SIMD
-    s.t_plane = std::ceil(waves / (kCUs * kSimdPerCU)) * rows * per_row * kCyclesPerWaveInstr / kClock;
+    s.t_plane = std::ceil(waves / (kCUs * kSimdPerCU)) * per_wave * kCyclesPerWaveInstr / kClock;
     // wind-up rows are re-read from HBM; the overlapped halo columns of
     // neighbouring strips mostly come from L2
     const double cells = nx * ny;
@@ -86,21 +90,24 @@ Pass model_3d(const stencil_plan_s *p, int K) {
     const double nty = std::ceil(ny / ty), nseg = std::ceil(nz / lz);
     const double blocks = ntx * nty * nseg;
     const double planes = lz + 2.0 * K * R;
+    // stage s starts 2sR planes into the stream
+    const double stage_planes = K * (lz + (K - 1.0) * R);
     // load-only wavefronts: those whose rows all lie in the outer R rows
     const double rpw = 64.0 / wl;
     const double load_only = 2.0 * std::floor(R / rpw);
     const double compute = nw - load_only;
-    const double per_plane_compute = K * (vec * (6.0 * R + 1.0) + 2.0 * R + kRowStage3D) + kRow3D;
-    const double instr_block_plane = compute * per_plane_compute + load_only * kLoadOnly3D;
+    const double per_stage_plane = vec * (6.0 * R + 1.0) + 2.0 * R + kRowStage3D;
+    const double instr_block = planes * (compute * kRow3D + load_only * kLoadOnly3D) +
+                               stage_planes * compute * per_stage_plane;
     Pass s;
-    s.t_valu = blocks * planes * instr_block_plane * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
+    s.t_valu = blocks * instr_block * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
     // one workgroup per CU at a time (1024 threads, <= 128 VGPRs): the
-    // plane loop of each CU's blocks runs back to back
+    // plane loop of each CU's blocks runs back to back, each plane its
+    // SIMD's share of the issue plus the barrier/LDS latency
     const double waves_per_simd = std::ceil(nw / kSimdPerCU);
-    const double issue_cycles = waves_per_simd * (instr_block_plane / nw) * kCyclesPerWaveInstr;
-    const double plane_cycles = issue_cycles + kPlaneLatency3D;
+    const double issue_cycles = waves_per_simd * (instr_block / nw) * kCyclesPerWaveInstr;
     const double rounds = std::ceil(blocks / kCUs);
-    s.t_plane = rounds * planes * plane_cycles / kClock;
+    s.t_plane = rounds * (issue_cycles + planes * kPlaneLatency3D) / kClock;
     const double cells = nx * ny * nz;
     s.t_hbm = (cells * 4.0 * (planes / lz) * (nt / ty) + cells * 4.0) / kHbmEff3D;
     return s;

@@ -12,7 +12,8 @@
 //     written with one 128-bit access per lane.
 //   * The wavefront streams rows y0-K*R .. y1-1+K*R of its y-segment.  Stage
 //     s (1..K) applies one time step and runs R rows behind stage s-1, like
-//     the paper's PE chain.  Each stage keeps the last 2R+1 rows of its input
+//     the paper's PE chain; it starts once its first needed row
+//     (y0-(K-s)*R) is due, 2*s*R rows into the stream.  Each stage keeps the last 2R+1 rows of its input
 //     in a register queue: the y-neighbours.  The x-neighbours of the
 //     queue's centre row come from the lane's own registers and, across the
 //     lane boundary, from the adjacent lanes through DPP wave shifts.  Only
@@ -184,6 +185,10 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
 
         static_for<1, K + 1>([&](auto sc) STAR_INLINE {
             constexpr int S = decltype(sc)::value;
+            // Stage S first produces a row that an output depends on at
+            // iteration 2*S*R; before that its window still holds wind-up
+            // rows and nothing reads what it would produce.
+            if (n < 2 * S * R) return;
             const int r = j - S * R;  // row produced by stage S
             float res[VEC];
             if constexpr (S == 1)

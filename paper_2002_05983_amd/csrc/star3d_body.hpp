@@ -16,7 +16,8 @@
 //   * Rows: the tile's TY output rows, (K-1)*R computed halo rows per side
 //     (stages 1..K-1 produce the values the next stage's halo needs), and R
 //     load-only rows per side that only supply stage 1's y-neighbours.
-//   * z is streamed.  Stage s (1..K) runs R planes behind stage s-1; each
+//   * z is streamed.  Stage s (1..K) runs R planes behind stage s-1 and
+//     starts 2*s*R planes into the stream, at its first needed plane; each
 //     stage keeps the last 2R+1 planes of its input column in registers (the
 //     z-neighbours).  Per plane, every stage writes its centre plane row to
 //     LDS (double-buffered), one barrier, then reads its y-neighbours from
@@ -237,6 +238,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
         if (!load_only) {
             static_for<2, K + 1>([&](auto sc) STAR_INLINE {
                 constexpr int S = decltype(sc)::value;
+                if (n < 2 * S * R) return;  // stage S not started (below)
                 lds_write_row<VEC, WL>(lds_row(S - 1, b, trow), lr, q[S - 2][(PS - R + P) % P]);
             });
         }
@@ -244,6 +246,10 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
         if (!load_only) {
             static_for<1, K + 1>([&](auto sc) STAR_INLINE {
                 constexpr int S = decltype(sc)::value;
+                // Stage S first produces a plane that an output depends on at
+                // iteration 2*S*R (workgroup-uniform); before that nothing
+                // reads what it would produce.
+                if (n < 2 * S * R) return;
                 const int r = zl - S * R;  // plane produced by stage S
                 float res[VEC];
                 if constexpr (S == 1)
