@@ -7,11 +7,13 @@ each radius with its plan's temporal degree K.  Inputs are resident in HBM
 before timing starts.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-tune] [--no-3d]
-                  [--no-high] [--no-precision] [--no-batch]
+                  [--no-single] [--no-high] [--no-precision] [--no-batch]
 
 Each plan is autotuned (every feasible kernel configuration timed at the
 real shape) before the timed region.  Secondary legs, reported under
-"extra": 2D radius 5..8 on the same grid (200 steps each); the 3D workload
+"extra": plain single-step (K=1) sweeps of the 2D grid and a 512^3 grid
+against the HBM peak and a device copy; 2D radius 5..8 on the same grid
+(200 steps each); the 3D workload
 (512^3, radius 1..4, 200 steps each) measured the same way; the precision form (768^3 radius 4, 1000 steps, FP32 against
 FP16/BF16 storage re-anchored every 10 or 50 steps, with errors); and the
 batched form (256 mixed 2D/3D grids, 100 steps, one captured batch against
@@ -205,6 +207,64 @@ def bench_2d_high(stencil, synth, torch, dev, side=SIDE, time_steps=200, reps=2,
                         f"per radius, clamp", "GCell/s": round(total, 1), "per_radius": rows}
 
 
+def bench_single_step(stencil, synth, torch, dev, side2=SIDE, side3=512, time_steps=20, reps=3):
+    """Plain single-step sweeps (K = 1: one read and one write of the grid per
+    step, 8 B per cell update): 2D r=1..4 on side2^2 and 3D r=1..4 on side3^3,
+    FP32 U[0,1), each radius in the best of a few K = 1 configurations, as
+    fractions of the 8 TB/s HBM peak and of a plain device copy of the same
+    grid timed alongside."""
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(torch.cuda.current_stream(dev))
+        for _ in range(reps):
+            fn()
+        b.record(torch.cuda.current_stream(dev))
+        torch.cuda.synchronize(dev)
+        return a.elapsed_time(b) / reps
+    out = {}
+    for ndim, shape in ((2, (side2, side2)), (3, (side3, side3, side3))):
+        x = torch.from_numpy(synth.grid_uniform(ndim, shape)).to(dev)
+        y = torch.empty_like(x)
+        copy_gbs = 2 * x.numel() * 4 / (timed(lambda: y.copy_(x)) / 1e3) / 1e9
+        rows = []
+        if ndim == 2:
+            cands = [f"k=1,ly={ly}" for ly in (64, 128, 256)]
+        else:
+            cands = [f"k=1,wl={wl},vec={v},nw=16,lz={lz}" for wl, v in ((32, 4), (64, 4), (64, 8))
+                     for lz in (64, 128, 256)]
+        for r in RADII:
+            c = synth.coefficients(3000 + 10 * ndim + r, ndim, r)
+            # best of the K = 1 configurations, timed on this grid
+            best = None
+            for cfg in cands:
+                try:
+                    p = stencil.Plan(shape, r, c, tune=cfg)
+                except Exception:
+                    continue  # rejected for this radius (e.g. 8 cells per lane)
+                try:
+                    ms = timed(lambda: p.run(x, y, time_steps))
+                except Exception:
+                    ms = None
+                p.close()
+                if ms is not None and (best is None or ms < best[0]):
+                    best = (ms, cfg)
+            p = stencil.Plan(shape, r, c, tune=best[1])
+            ms = timed(lambda: p.run(x, y, time_steps))
+            gc = x.numel() * time_steps / (ms / 1e3) / 1e9
+            rows.append({"radius": r, "GCell/s": round(gc, 1), "GB/s": round(gc * 8, 1),
+                         "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
+                         "pct_of_copy": round(100 * gc * 8 / copy_gbs, 1), "config": p.describe()})
+            p.close()
+        out[f"{ndim}d"] = {"grid": list(shape), "copy_GB/s": round(copy_gbs, 1), "per_radius": rows}
+        del x, y
+        torch.cuda.empty_cache()
+    out["workload"] = (f"single-step (K=1) FP32 sweeps, {time_steps} steps: 2D r=1..4 on "
+                       f"{side2}^2, 3D r=1..4 on {side3}^3, U[0,1) grids, clamp")
+    return out
+
+
 def read_precision_reference():
     """FP64 oracle values of the reduced precision workload (128^3, radius 4,
     1000 steps) on sampled cells, from the fixture its generator wrote."""
@@ -365,6 +425,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-high", action="store_true", help="skip the 2D radius 5..8 leg")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-step (K=1) leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
     ap.add_argument("--time-steps", type=int, default=TIME_STEPS, help=argparse.SUPPRESS)
     ap.add_argument("--config", action="append", default=[], metavar="R:TUNE", help=argparse.SUPPRESS)
@@ -505,6 +566,9 @@ def main():
     torch.cuda.empty_cache()
     progress(f"2D: {value:.1f} GCell/s")
     extra = {}
+    if not args.no_single:
+        extra["single_step"] = bench_single_step(stencil, synth, torch, dev, side2=side)
+        progress("single-step sweeps done")
     if not args.no_high:
         extra["2d_high_radius"] = bench_2d_high(stencil, synth, torch, dev, side=side,
                                                 tune=not args.no_tune)
