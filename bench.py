@@ -13,7 +13,7 @@ Each plan is autotuned (every feasible kernel configuration timed at the
 real shape) before the timed region.  Secondary legs, reported under
 "extra": plain single-step (K=1) sweeps of the 2D grid and a 512^3 grid
 against the HBM peak and a device copy; 2D radius 5..8 on the same grid
-(200 steps each); the 3D workload
+(200 steps each) and 3D radius 5..8 on 512^3 (50 steps each); the 3D workload
 (512^3, radius 1..4, 200 steps each) measured the same way; the precision form (768^3 radius 4, 1000 steps, FP32 against
 FP16/BF16 storage re-anchored every 10 or 50 steps, with errors); and the
 batched form (256 mixed 2D/3D grids, 100 steps, one captured batch against
@@ -265,6 +265,39 @@ def bench_single_step(stencil, synth, torch, dev, side2=SIDE, side3=512, time_st
     return out
 
 
+def bench_3d_high(stencil, synth, torch, dev, side=512, time_steps=50, reps=2):
+    """3D star stencils r=5..8 on side^3 FP32 (U[0,1)), time_steps steps each:
+    the single-step kernel (the only one built for these radii in 3D)."""
+    shape = (side, side, side)
+    x = torch.from_numpy(synth.grid_uniform(2, shape)).to(dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    rows, tot_ms = [], 0.0
+    radii = (5, 6, 7, 8)
+    for r in radii:
+        p = stencil.Plan(shape, r, synth.coefficients(2000 + r, 3, r))
+        p.run(x, y, time_steps, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(stream)
+        for _ in range(reps):
+            p.run(x, y, time_steps, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b) / reps
+        tot_ms += ms
+        gc = x.numel() * time_steps / (ms / 1e3) / 1e9
+        rows.append({"radius": r, "ms": round(ms, 3), "GCell/s": round(gc, 1),
+                     "GFLOP/s": round(gc * flop_per_cell(3, r), 1),
+                     "pct_hbm_roofline": round(100 * gc * 8 / PEAK_HBM_GBS, 1),
+                     "config": p.describe()})
+        p.close()
+    total = x.numel() * time_steps * len(radii) / (tot_ms / 1e3) / 1e9
+    return {"workload": f"3D star stencils r=5..8, {side}^3 FP32 U[0,1), {time_steps} steps per "
+                        f"radius, clamp, single-step kernel", "GCell/s": round(total, 1),
+            "per_radius": rows}
+
+
 def read_precision_reference():
     """FP64 oracle values of the reduced precision workload (128^3, radius 4,
     1000 steps) on sampled cells, from the fixture its generator wrote."""
@@ -424,7 +457,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the secondary 3D leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
-    ap.add_argument("--no-high", action="store_true", help="skip the 2D radius 5..8 leg")
+    ap.add_argument("--no-high", action="store_true", help="skip the radius 5..8 legs")
     ap.add_argument("--no-single", action="store_true", help="skip the single-step (K=1) leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
     ap.add_argument("--time-steps", type=int, default=TIME_STEPS, help=argparse.SUPPRESS)
@@ -573,6 +606,8 @@ def main():
         extra["2d_high_radius"] = bench_2d_high(stencil, synth, torch, dev, side=side,
                                                 tune=not args.no_tune)
         progress(f"2D r=5..8: {extra['2d_high_radius']['GCell/s']} GCell/s")
+        extra["3d_high_radius"] = bench_3d_high(stencil, synth, torch, dev)
+        progress(f"3D r=5..8: {extra['3d_high_radius']['GCell/s']} GCell/s")
     if not args.no_3d:
         extra["3d"] = bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)
         progress(f"3D: {extra['3d']['GCell/s']} GCell/s")

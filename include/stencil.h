@@ -1,8 +1,8 @@
 /*
  * stencil.h -- C ABI of the MI355X (gfx950) star-stencil library.
  *
- * The library applies repeated time steps of a 2D star stencil of radius
- * 1..8 or a 3D star stencil of radius 1..4 (Zohouri, Podobas, Matsuoka, "High-Performance High-Order
+ * The library applies repeated time steps of a 2D or 3D star stencil of
+ * radius 1..8 (Zohouri, Podobas, Matsuoka, "High-Performance High-Order
  * Stencil Computation on FPGAs Using OpenCL", IPDPSW 2018, Sec. IV.A,
  * Eq. (1)):
  *
@@ -75,9 +75,12 @@ enum stencil_storage {
  *   ndim     2 or 3.
  *   dims     ndim extents in x, y[, z] order, each >= 1; the cell count times
  *            4 bytes must fit in int64.
- *   radius   1..8 in 2D, 1..4 in 3D (EUNSUPPORTED for a 3D radius of 5..8;
- *            the paper's 2D/3D diffusion stencils have radius 1..4, the
- *            higher 2D radii follow its scaling discussion in Sec. VI.A).
+ *   radius   1..8.  The paper's diffusion stencils have radius 1..4; the
+ *            higher radii follow its scaling discussion (Sec. VI.A).  A 3D
+ *            plan of radius 5..8 runs the single-step kernel ("naive",
+ *            one launch per step: the 3D streaming kernels are built for
+ *            radius 1..4) and takes no other configuration (EUNSUPPORTED);
+ *            low-precision storage is built for radius 1..4 (EUNSUPPORTED).
  *   coeffs   host array of ncoeffs FP32 values in the order given above.
  *   ncoeffs  must equal 1 + 2*ndim*radius.
  *   boundary STENCIL_BOUNDARY_CLAMP (the only boundary of the paper).

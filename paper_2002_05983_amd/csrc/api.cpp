@@ -91,8 +91,6 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
     if (ndim != 2 && ndim != 3) return fail(STENCIL_EINVAL, "ndim must be 2 or 3 (got %d)", ndim);
     if (!dims) return fail(STENCIL_EINVAL, "dims is NULL");
     if (radius < 1 || radius > 8) return fail(STENCIL_EINVAL, "radius must be 1..8 (got %d)", radius);
-    if (ndim == 3 && radius > 4)
-        return fail(STENCIL_EUNSUPPORTED, "3D kernels are built for radius 1..4 (got %d)", radius);
     if (!coeffs) return fail(STENCIL_EINVAL, "coeffs is NULL");
     const int npts = 1 + 2 * ndim * radius;
     if (ncoeffs != npts)

@@ -12,8 +12,8 @@
 
 namespace star {
 
-// Largest point count: a radius-8 2D star (1 + 2*2*8; a radius-4 3D star has 25).
-constexpr int kMaxPoints = 33;
+// Largest point count: a radius-8 3D star (1 + 2*3*8).
+constexpr int kMaxPoints = 49;
 
 // Per-point coefficients, passed by value in the kernel argument segment so
 // that every coefficient is a scalar register operand of the FMA chain.

@@ -53,7 +53,7 @@ hipError_t launch_naive(int ndim, int R, const float *src, float *dst, int nx, i
 #define CASE(ND, RR) \
     if (ndim == ND && R == RR) return launch_one<ND, RR>(src, dst, nx, ny, nz, cf, stream);
     CASE(2, 1) CASE(2, 2) CASE(2, 3) CASE(2, 4) CASE(2, 5) CASE(2, 6) CASE(2, 7) CASE(2, 8)
-    CASE(3, 1) CASE(3, 2) CASE(3, 3) CASE(3, 4)
+    CASE(3, 1) CASE(3, 2) CASE(3, 3) CASE(3, 4) CASE(3, 5) CASE(3, 6) CASE(3, 7) CASE(3, 8)
 #undef CASE
     return hipErrorInvalidValue;
 }

@@ -71,6 +71,8 @@ static int plan_apply(stencil_plan_s *p, const char *tune);
 int plan_configure(stencil_plan_s *p, const char *tune) {
     if (p->storage != STENCIL_F32 && p->ndim != 3)
         return star_set_error(STENCIL_EUNSUPPORTED, "low-precision storage is built for 3D grids");
+    if (p->storage != STENCIL_F32 && p->radius > 4)
+        return star_set_error(STENCIL_EUNSUPPORTED, "low-precision storage is built for radius 1..4");
     if (tune && *tune) {
         const int rc = plan_apply(p, tune);
         p->tuned_by = "override";
@@ -92,6 +94,12 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->variant = STAR_S2D;
         p->K = default_k2d(R);
         p->ly = 0;
+    } else if (R > kMaxR3D) {
+        // 3D radius 5..8 runs the single-step kernel: the streaming kernel's
+        // z-queue of 2R+1 planes and its 2R halo rows per 32-row tile do not
+        // fit a 1024-thread workgroup's 128 VGPRs above radius 4
+        p->variant = STAR_NAIVE;
+        p->K = 1;
     } else {
         // defaults measured on a 512^3 grid
         p->variant = STAR_S3D;
@@ -127,6 +135,9 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 p->K = v;
             } else if (key == "ly" && p->ndim == 2) {
                 p->ly = v;
+            } else if (p->ndim == 3 && R > kMaxR3D) {
+                return star_set_error(STENCIL_EUNSUPPORTED,
+                                      ("3D radius 5..8 has no streaming configuration ('" + item + "')").c_str());
             } else if (key == "lz" && p->ndim == 3) {
                 p->s3_lz = v;
             } else if (key == "nw" && p->ndim == 3) {

@@ -156,7 +156,7 @@ def test_batch_hands_lowp_zero_step_and_high_radius_grids_to_their_plans(torch, 
     ref16 = torch.empty_like(x16)
     plan16.run(x16, ref16, 7)
     data = make_inputs([((50, 300), 3, 6), ((12, 30, 40), 1, 5), ((20, 20), 1, 0),
-                        ((40, 600), 7, 5)], 7310)
+                        ((40, 600), 7, 5), ((8, 12, 40), 6, 3)], 7310)
     plans, ins, outs, steps = build(torch, st, data)
     refs = []
     for p, x, s in zip(plans, ins, steps):

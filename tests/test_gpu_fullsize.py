@@ -1,6 +1,6 @@
 """Full-size parity in the launch configurations the benchmark times.
 
-The 16384^2 2D grid at R = 1..8, the 512^3 3D grid at R = 1..4 and the
+The 16384^2 2D grid at R = 1..8, the 512^3 3D grid at R = 1..8 and the
 768^3 grid at R = 4 (the workloads bench.py measures, with its seeds), each
 plan autotuned as bench.py does, run for three passes plus a tail pass, and
 checked on sampled cells -- corners, face centres and random interior
@@ -89,7 +89,7 @@ def grid3d():
     return synth.grid_uniform(2, (512, 512, 512))
 
 
-@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("radius", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_3d_512cube_bench_configuration(torch, st, oracle_mod, grid3d, radius):
     c = synth.coefficients(2000 + radius, 3, radius)
     check_sampled(torch, st, oracle_mod, grid3d, c, radius, what=f"3D R{radius}")

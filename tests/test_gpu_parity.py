@@ -140,6 +140,36 @@ def test_s3d_default_config_vs_fp64(torch, st, oracle_mod, radius):
     assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 12)) <= TOL_F64
 
 
+S3D_HIGH_SHAPES = [(1, 1, 1), (3, 4, 10), (9, 17, 33), (20, 37, 300), (6, 3, 257)]
+
+
+@pytest.mark.parametrize("radius", [5, 6, 7, 8])
+@pytest.mark.parametrize("shape", S3D_HIGH_SHAPES)
+def test_3d_high_radius_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    """3D radius 5..8 (the single-step kernel), sides below and above R."""
+    c = synth.coefficients(800 + radius, 3, radius)
+    f = synth.grid_uniform(900 + radius, shape)
+    for steps in (1, 4):
+        got, desc = gpu_run(torch, st, f, radius, c, steps)
+        assert "variant=naive" in desc, desc
+        assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, steps), f"3D {shape} r{radius}")
+    assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 4)) <= TOL_F64
+
+
+def test_3d_high_radius_autotune_has_one_candidate(torch, st):
+    shape = (24, 40, 72)
+    f = synth.grid_uniform(950, shape)
+    plan = st.Plan(shape, 6, synth.coefficients(951, 3, 6))
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    rows = plan.autotune(x, y)
+    assert [cfg for cfg, _ in rows] == ["naive"] and rows[0][1] > 0
+    assert "variant=naive" in plan.describe()
+    with pytest.raises(st.StencilError):
+        st.Plan(shape, 6, synth.coefficients(951, 3, 6), tune="k=1,wl=32")
+    plan.close()
+
+
 def test_config1_2d_r1_1024_10_steps(torch, st, oracle_mod):
     """2D radius 1 on 1024x1024, U[0,1) values, seeded coefficients, 10 steps."""
     c = synth.coefficients(101, 2, 1)

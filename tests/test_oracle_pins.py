@@ -143,6 +143,30 @@ def test_high_radius_2d_pins(oracle_mod, radius, shape):
                                    rtol=1e-13, atol=1e-14)
 
 
+@pytest.mark.parametrize("radius", [5, 6, 7, 8])
+@pytest.mark.parametrize("shape", [(3, 4, 10), (9, 2, 3), (1, 1, 12)])
+def test_high_radius_3d_pins(oracle_mod, radius, shape):
+    """3D radius 5..8: unit-coefficient shifts along every axis equal
+    edge-padded shifts, and oracle(f, s) equals A^s f on grids whose sides
+    are below and above the radius."""
+    f = synth.grid_uniform(19, shape)
+    for i in (1, radius - 1, radius):
+        for d in DIRS[3]:
+            c = np.zeros(1 + 6 * radius, dtype=np.float32)
+            c[coef_index(3, d, i)] = 1.0
+            want = edge_shift(f.astype(np.float64), d, i)
+            np.testing.assert_array_equal(oracle_mod.star_run_f64(f, c, radius, 1), want)
+            np.testing.assert_array_equal(oracle_mod.star_run_f32(f, c, radius, 1),
+                                          want.astype(np.float32))
+    c = synth.coefficients(170 + radius, 3, radius).astype(np.float64)
+    A = dense_operator(shape, 3, radius, c)
+    g = f.astype(np.float64)
+    for s in (1, 3):
+        want = (np.linalg.matrix_power(A, s) @ g.ravel()).reshape(shape)
+        np.testing.assert_allclose(oracle_mod.star_run_f64(g, c, radius, s), want,
+                                   rtol=1e-13, atol=1e-14)
+
+
 @pytest.mark.parametrize("shape", [(13, 17), (6, 7, 9)])
 def test_linearity(oracle_mod, shape):
     ndim = len(shape)
