@@ -76,11 +76,11 @@ enum stencil_storage {
  *   dims     ndim extents in x, y[, z] order, each >= 1; the cell count times
  *            4 bytes must fit in int64.
  *   radius   1..8.  The paper's diffusion stencils have radius 1..4; the
- *            higher radii follow its scaling discussion (Sec. VI.A).  A 3D
- *            plan of radius 5..8 runs the single-step kernel ("naive",
- *            one launch per step: the 3D streaming kernels are built for
- *            radius 1..4) and takes no other configuration (EUNSUPPORTED);
- *            low-precision storage is built for radius 1..4 (EUNSUPPORTED).
+ *            higher radii follow its scaling discussion (Sec. VI.A).  In 3D
+ *            above radius 4 only single-step passes are built (the
+ *            streaming kernel at k = 1, or the one-thread-per-cell kernel,
+ *            the default at radius 7 and 8); low-precision storage is built
+ *            for radius 1..4 (EUNSUPPORTED above).
  *   coeffs   host array of ncoeffs FP32 values in the order given above.
  *   ncoeffs  must equal 1 + 2*ndim*radius.
  *   boundary STENCIL_BOUNDARY_CLAMP (the only boundary of the paper).

@@ -53,9 +53,6 @@ struct Star3DArgs {
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
     Coefs cf;
 };
-// Largest 3D radius of the streaming kernel (higher radii run the
-// single-step kernel).
-constexpr int kMaxR3D = 4;
 // Largest K built per radius: the tile keeps >= 8 output rows of 16 for
 // R = 1 and every build stays within 128 VGPRs without spilling.
 constexpr int max_k3d(int R) { return R == 1 ? 4 : R == 2 ? 2 : 1; }
@@ -66,5 +63,9 @@ hipError_t launch_star3d_r1(const Star3DArgs &a, hipStream_t stream);
 hipError_t launch_star3d_r2(const Star3DArgs &a, hipStream_t stream);
 hipError_t launch_star3d_r3(const Star3DArgs &a, hipStream_t stream);
 hipError_t launch_star3d_r4(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r5(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r6(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r7(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_r8(const Star3DArgs &a, hipStream_t stream);
 
 }  // namespace star

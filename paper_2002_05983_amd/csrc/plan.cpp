@@ -94,12 +94,6 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->variant = STAR_S2D;
         p->K = default_k2d(R);
         p->ly = 0;
-    } else if (R > kMaxR3D) {
-        // 3D radius 5..8 runs the single-step kernel: the streaming kernel's
-        // z-queue of 2R+1 planes and its 2R halo rows per 32-row tile do not
-        // fit a 1024-thread workgroup's 128 VGPRs above radius 4
-        p->variant = STAR_NAIVE;
-        p->K = 1;
     } else {
         // defaults measured on a 512^3 grid
         p->variant = STAR_S3D;
@@ -108,6 +102,12 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->s3_rows = 16;
         p->s3_lanes = 32;
         p->s3_lz = 0;
+        // Above radius 4 the streaming kernel's z-queue of 2R+1 planes no
+        // longer fits a 1024-thread workgroup's 128 VGPRs (it spills) and 2R
+        // of its 32 tile rows are halo: measured on 512^3 it is 3.5x and
+        // 1.7x the single-step kernel at R = 5, 6, and about even at 7, 8,
+        // where the single-step kernel is the default
+        if (R >= 7) p->variant = STAR_NAIVE;
     }
     p->ly = (p->ndim == 2) ? 0 : p->ly;
     if (tune && *tune) {
@@ -135,17 +135,18 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 p->K = v;
             } else if (key == "ly" && p->ndim == 2) {
                 p->ly = v;
-            } else if (p->ndim == 3 && R > kMaxR3D) {
-                return star_set_error(STENCIL_EUNSUPPORTED,
-                                      ("3D radius 5..8 has no streaming configuration ('" + item + "')").c_str());
             } else if (key == "lz" && p->ndim == 3) {
                 p->s3_lz = v;
+                p->variant = STAR_S3D;
             } else if (key == "nw" && p->ndim == 3) {
                 p->s3_rows = v;
+                p->variant = STAR_S3D;
             } else if (key == "vec" && p->ndim == 3) {
                 p->vec = v;
+                p->variant = STAR_S3D;
             } else if (key == "wl" && p->ndim == 3) {
                 p->s3_lanes = v;
+                p->variant = STAR_S3D;
 
             } else {
                 return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
@@ -173,7 +174,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             if (p->s3_lz == 0) p->s3_lz = 256;  // z-segments of whole 64^3 storage tiles
         }
         if (p->K < 1 || p->K > max_k3d(R))
-            return star_set_error(STENCIL_EINVAL, "3D k must be in 1..4/2/1/1 for R = 1..4");
+            return star_set_error(STENCIL_EINVAL, "3D k must be 1..4 for R = 1, 1..2 for R = 2, 1 above");
         if (p->s3_lanes != 64 && p->s3_lanes != 32)
             return star_set_error(STENCIL_EINVAL, "3D wl must be 64 or 32");
         const int rows = p->s3_rows * (64 / p->s3_lanes);
@@ -275,6 +276,10 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
                 case 2: return launch_star3d_r2(a, stream);
                 case 3: return launch_star3d_r3(a, stream);
                 case 4: return launch_star3d_r4(a, stream);
+                case 5: return launch_star3d_r5(a, stream);
+                case 6: return launch_star3d_r6(a, stream);
+                case 7: return launch_star3d_r7(a, stream);
+                case 8: return launch_star3d_r8(a, stream);
             }
             return hipErrorInvalidValue;
         }

@@ -80,7 +80,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     constexpr int RPW = 64 / WL;      // tile rows per wavefront
     constexpr int W = WL * VEC;       // columns per tile row
     constexpr int ROWF = W;           // floats per LDS row
-    static_assert(R <= VEC && VEC % 4 == 0 && 64 % WL == 0, "bad vector width");
+    static_assert(R <= 2 * VEC && VEC % 4 == 0 && 64 % WL == 0, "bad vector width");
     extern __shared__ float lds[];    // [K][2][NT][ROWF]
 
     const int lane = threadIdx.x & 63;
@@ -171,15 +171,24 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
                      int b, float (&res)[VEC]) STAR_INLINE {
         constexpr int NS = decltype(nsc)::value;
         constexpr int CS = decltype(csc)::value;
+        // the wavefront's end lanes take their own border cell (general
+        // form) or zero (interior form: they hold halo columns)
+        auto lower = [&](float v) STAR_INLINE {
+            return EDGE ? from_lower_lane(v, q[CS][0]) : from_lower_lane_or_zero(v);
+        };
+        auto upper = [&](float v) STAR_INLINE {
+            return EDGE ? from_upper_lane(v, q[CS][VEC - 1]) : from_upper_lane_or_zero(v);
+        };
+        // left[k]: column base - k; right[k]: column base + VEC - 1 + k
         float left[R + 1], right[R + 1];
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
-            if constexpr (EDGE) {
-                left[k] = from_lower_lane(q[CS][VEC - k], q[CS][0]);
-                right[k] = from_upper_lane(q[CS][k - 1], q[CS][VEC - 1]);
-            } else {  // the wavefront's end lanes hold halo columns
-                left[k] = from_lower_lane_or_zero(q[CS][VEC - k]);
-                right[k] = from_upper_lane_or_zero(q[CS][k - 1]);
+            if (k <= VEC) {  // the adjacent lane
+                left[k] = lower(q[CS][VEC - k]);
+                right[k] = upper(q[CS][k - 1]);
+            } else {  // two lanes away (R > VEC)
+                left[k] = lower(lower(q[CS][2 * VEC - k]));
+                right[k] = upper(upper(q[CS][k - VEC - 1]));
             }
         }
         float acc[VEC];
@@ -338,6 +347,7 @@ template <int R, int K, int VEC, int WL>
 constexpr int prefetch3() {
     constexpr int P = 2 * R + 1;
     if constexpr (K > 1) return P;
+    if constexpr (R > 4) return 1;  // high radius: the z-window alone nears the budget
     if constexpr (VEC == 4 && WL == 32) return P + 3 > 12 ? 3 : 12 - P;  // two rows per wave
     if constexpr (VEC == 4) return P + 4 > 12 ? 4 : 12 - P;  // ring of max(12, P + 4) planes
     return 8 - P > 2 ? 8 - P : 2;                            // ring of max(8, P + 2) planes

@@ -53,9 +53,9 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
     std::vector<std::string> out;
     const int R = p->radius;
     char buf[96];
-    if (p->ndim == 3 && R > kMaxR3D) {
-        out.push_back("naive");  // the only kernel built for 3D radius 5..8
-    } else if (p->ndim == 2) {
+    if (p->ndim == 3 && R > 4 && p->storage == STENCIL_F32)
+        out.push_back("naive");  // competitive with the spilling 3D kernel above radius 4
+    if (p->ndim == 2) {
         for (int K = 1; K <= max_k2d(R); ++K)
             for (int ly : {64, 96, 128, 192, 256, 384}) {
                 if (ly > p->ny && ly != 64) continue;

@@ -146,27 +146,38 @@ S3D_HIGH_SHAPES = [(1, 1, 1), (3, 4, 10), (9, 17, 33), (20, 37, 300), (6, 3, 257
 @pytest.mark.parametrize("radius", [5, 6, 7, 8])
 @pytest.mark.parametrize("shape", S3D_HIGH_SHAPES)
 def test_3d_high_radius_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
-    """3D radius 5..8 (the single-step kernel), sides below and above R."""
+    """3D radius 5..8, sides below and above R: the default configuration,
+    the single-step kernel and streaming tiles of 32 rows (two per
+    wavefront) and 16 rows."""
     c = synth.coefficients(800 + radius, 3, radius)
     f = synth.grid_uniform(900 + radius, shape)
-    for steps in (1, 4):
-        got, desc = gpu_run(torch, st, f, radius, c, steps)
-        assert "variant=naive" in desc, desc
-        assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, steps), f"3D {shape} r{radius}")
+    want = {s: oracle_mod.star_run_f32(f, c, radius, s) for s in (1, 4)}
+    tunes = [None, "naive", "k=1,wl=32,nw=16,lz=7", "k=1,wl=32,nw=12,lz=64"]
+    if radius < 8:
+        tunes.append("k=1,wl=64,nw=16,lz=5")  # 16 rows hold 2R halo rows up to R = 7
+    for tune in tunes:
+        for steps in (1, 4):
+            got, desc = gpu_run(torch, st, f, radius, c, steps, tune=tune)
+            assert_bitwise(got, want[steps], f"3D {shape} r{radius} {desc}")
     assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 4)) <= TOL_F64
 
 
-def test_3d_high_radius_autotune_has_one_candidate(torch, st):
+def test_3d_high_radius_autotune(torch, st, oracle_mod):
     shape = (24, 40, 72)
     f = synth.grid_uniform(950, shape)
-    plan = st.Plan(shape, 6, synth.coefficients(951, 3, 6))
+    c = synth.coefficients(951, 3, 6)
+    plan = st.Plan(shape, 6, c)
     x = torch.from_numpy(f).cuda()
     y = torch.empty_like(x)
     rows = plan.autotune(x, y)
-    assert [cfg for cfg, _ in rows] == ["naive"] and rows[0][1] > 0
-    assert "variant=naive" in plan.describe()
-    with pytest.raises(st.StencilError):
-        st.Plan(shape, 6, synth.coefficients(951, 3, 6), tune="k=1,wl=32")
+    cfgs = [cfg for cfg, _ in rows]
+    assert "naive" in cfgs and any(cfg.startswith("k=1,wl=") for cfg in cfgs)
+    assert all("k=2" not in cfg for cfg in cfgs)  # single-step passes only above radius 4
+    plan.run(x, y, 3)
+    torch.cuda.synchronize()
+    assert_bitwise(y.cpu().numpy(), oracle_mod.star_run_f32(f, c, 6, 3), "3D r6 tuned")
+    with pytest.raises(ValueError):  # EINVAL: one step per pass above radius 4
+        st.Plan(shape, 6, c, tune="k=2")
     plan.close()
 
 
