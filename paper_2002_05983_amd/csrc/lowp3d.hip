@@ -247,6 +247,9 @@ __global__ __launch_bounds__(1024) void lowp3d_step(LowpArgs a, int hx, int tx, 
         lds_write_row4(lds_row(b, trow), lr, win[(PH - R + P) % P]);
         __syncthreads();
         if (load_only) return;
+        // the first plane an output needs (z0) is produced 2R planes into
+        // the stream; earlier planes are wind-up that nothing reads
+        if (n < 2 * R) return;
         constexpr int CS = (PH - R + P) % P;
         float left[R + 1], right[R + 1];
 #pragma unroll
