@@ -101,6 +101,15 @@ def test_3d_768cube_r4_bench_configuration(torch, st, oracle_mod):
     check_sampled(torch, st, oracle_mod, f, c, 4, what="768^3 R4")
 
 
+def test_2d_grid_beyond_2_31_cells(torch, st, oracle_mod):
+    """33000 x 65536 = 2.16e9 cells (> 2^31; 8.65 GB per grid): row offsets
+    and the store descriptors must not wrap in 32 bits."""
+    shape = (33000, 65536)
+    f = synth.grid_uniform(9, shape)
+    c = synth.coefficients(10, 2, 3)
+    check_sampled(torch, st, oracle_mod, f, c, 3, tune_first=False, what="2D 2.16e9 cells")
+
+
 def test_widest_3d_plane(torch, st, oracle_mod):
     """nx*ny*4 = 2^31 - 128 bytes per plane: the largest plane the 3D
     kernels address with 32-bit offsets."""
