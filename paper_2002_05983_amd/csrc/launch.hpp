@@ -50,6 +50,7 @@ struct Star3DArgs {
     int wl;       // lanes per tile row: 64 or 32 (two rows per wavefront)
     int nw;       // wavefronts per workgroup; tile rows = nw*64/wl incl. 2*K*R halo rows
     int lz;       // output planes per z-segment
+    bool pair;    // two planes per barrier (k = 1, vec = 4)
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
     Coefs cf;
 };

@@ -107,7 +107,9 @@ Pass model_3d(const stencil_plan_s *p, int K) {
     const double waves_per_simd = std::ceil(nw / kSimdPerCU);
     const double issue_cycles = waves_per_simd * (instr_block / nw) * kCyclesPerWaveInstr;
     const double rounds = std::ceil(blocks / kCUs);
-    s.t_plane = rounds * (issue_cycles + planes * kPlaneLatency3D) / kClock;
+    // one barrier and LDS round trip per plane, per pair of planes when paired
+    const double barriers = p->s3_pair ? std::ceil(planes / 2.0) : planes;
+    s.t_plane = rounds * (issue_cycles + barriers * kPlaneLatency3D) / kClock;
     const double cells = nx * ny * nz;
     s.t_hbm = (cells * 4.0 * (planes / lz) * (nt / ty) + cells * 4.0) / kHbmEff3D;
     return s;

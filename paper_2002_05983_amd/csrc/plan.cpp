@@ -102,6 +102,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->s3_rows = 16;
         p->s3_lanes = 32;
         p->s3_lz = 0;
+        p->s3_pair = 0;
         // Above radius 4 the streaming kernel's z-queue of 2R+1 planes no
         // longer fits a 1024-thread workgroup's 128 VGPRs (it spills) and 2R
         // of its 32 tile rows are halo: measured on 512^3 it is 3.5x and
@@ -147,6 +148,10 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             } else if (key == "wl" && p->ndim == 3) {
                 p->s3_lanes = v;
                 p->variant = STAR_S3D;
+            } else if (key == "pair" && p->ndim == 3) {
+                if (v != 1) return star_set_error(STENCIL_EINVAL, "pair takes the value 1");
+                p->s3_pair = 1;
+                p->variant = STAR_S3D;
 
             } else {
                 return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
@@ -167,9 +172,9 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             return star_set_error(STENCIL_EUNSUPPORTED, "3D planes must stay below 2^31 bytes");
         if (p->storage != STENCIL_F32) {
             // the low-precision passes are single-step, 4 cells per lane
-            if (p->K != 1 || (p->vec != 0 && p->vec != 4) || p->s3_lz % 64 != 0)
+            if (p->K != 1 || (p->vec != 0 && p->vec != 4) || p->s3_lz % 64 != 0 || p->s3_pair)
                 return star_set_error(STENCIL_EINVAL,
-                                      "low-precision storage runs k=1, vec=4, lz a multiple of 64");
+                                      "low-precision storage runs k=1, vec=4, lz a multiple of 64, unpaired");
             p->vec = 4;
             if (p->s3_lz == 0) p->s3_lz = 256;  // z-segments of whole 64^3 storage tiles
         }
@@ -182,9 +187,12 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             return star_set_error(STENCIL_EINVAL, "3D nw must be <= 16 with nw*64/wl > 2*k*R");
         const bool al = p->nx % 4 == 0;
         if (p->vec == 0)
-            p->vec = (p->s3_lanes == 64 && p->nx > 256 && p->nx <= 512 && vec8_ok(R, p->K, al)) ? 8 : 4;
+            p->vec = (p->s3_lanes == 64 && p->nx > 256 && p->nx <= 512 && vec8_ok(R, p->K, al) &&
+                      !p->s3_pair) ? 8 : 4;
         if (p->vec != 4 && !(p->vec == 8 && p->s3_lanes == 64 && vec8_ok(R, p->K, al)))
             return star_set_error(STENCIL_EINVAL, "3D vec must be 4, or 8 for wl=64, aligned k=1, R<=2");
+        if (p->s3_pair && (p->K != 1 || p->vec != 4))
+            return star_set_error(STENCIL_EINVAL, "pair=1 needs k=1 and vec=4");
         if (p->s3_lz == 0) p->s3_lz = default_lz(p);
         if (p->s3_lz < 1) return star_set_error(STENCIL_EINVAL, "lz must be >= 1");
         const int W = p->s3_lanes * p->vec;
@@ -268,6 +276,7 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
             a.nw = p->s3_rows;
             a.wl = p->s3_lanes;
             a.lz = p->s3_lz;
+            a.pair = p->s3_pair != 0 && k == 1;  // a tail pass of a K > 1 plan is not paired
             a.aligned = (p->nx % 4 == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
             if (a.vec == 8 && !a.aligned) a.vec = 4;
             a.cf = p->cf;
@@ -293,13 +302,13 @@ std::string plan_describe(const stencil_plan_s *p) {
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
     if (p->variant == STAR_S3D)
         snprintf(buf, sizeof buf,
-                 "variant=%s ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d%s by=%s",
+                 "variant=%s ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d%s%s by=%s",
                  p->storage == STENCIL_F32 ? "s3d"
                  : p->storage == STENCIL_F16 ? "s3d-f16"
                  : p->storage == STENCIL_BF16 ? "s3d-bf16"
                  : p->storage == STENCIL_F16_SCALED ? "s3d-f16-scaled" : "s3d-bf16-scaled",
                  p->radius, p->K, p->tile[0], p->tile[1], p->tile[2], p->vec, p->s3_lanes,
-                 p->s3_rows, p->s3_lz,
+                 p->s3_rows, p->s3_lz, p->s3_pair ? " pair=1" : "",
                  p->storage == STENCIL_F32 ? ""
                  : (" m=" + std::to_string(p->anchor_m)).c_str(),
                  p->tuned_by.c_str());

@@ -41,6 +41,7 @@ struct stencil_plan_s {
     int s3_lanes = 32;  // lanes along x per tile row
     int s3_rows = 16;   // tile rows (halo included) per workgroup
     int s3_lz = 64;     // output planes per z-segment
+    int s3_pair = 0;    // 1: two planes per barrier (single-step passes)
     std::string tuned_by = "default";
 };
 

@@ -14,7 +14,7 @@ namespace {
 using s3d::prefetch3;
 using s3d::star3d_body;
 
-template <int R, int K, int VEC, int WL, int D, bool ALIGNED>
+template <int R, int K, int VEC, int WL, int D, bool ALIGNED, bool PAIR>
 __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ src,
                                                       float *__restrict__ dst, int nx, int ny,
                                                       int nz, int hx, int tx, int ntx, int nty,
@@ -23,14 +23,14 @@ __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ 
     const int strip = lb % ntx, ytile = (lb / ntx) % nty, zseg = lb / (ntx * nty);
     const int nt = (blockDim.x >> 6) * (64 / WL);
     if (s3d::star3d_interior<R, K, VEC, WL>(nx, ny, nz, hx, tx, strip, ytile, zseg, lz, nt))
-        star3d_body<R, K, VEC, WL, D, ALIGNED, false>(src, dst, nx, ny, nz, hx, tx, strip, ytile,
-                                                      zseg, lz, cf);
+        star3d_body<R, K, VEC, WL, D, ALIGNED, false, PAIR>(src, dst, nx, ny, nz, hx, tx, strip,
+                                                            ytile, zseg, lz, cf);
     else
-        star3d_body<R, K, VEC, WL, D, ALIGNED, true>(src, dst, nx, ny, nz, hx, tx, strip, ytile,
-                                                     zseg, lz, cf);
+        star3d_body<R, K, VEC, WL, D, ALIGNED, true, PAIR>(src, dst, nx, ny, nz, hx, tx, strip,
+                                                           ytile, zseg, lz, cf);
 }
 
-template <int K, int VEC, int WL, bool AL>
+template <int K, int VEC, int WL, bool AL, bool PAIR = false>
 hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
     constexpr int R = STAR_R;
     constexpr int W = WL * VEC;
@@ -49,9 +49,10 @@ hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
     const int64_t blocks = (int64_t)ntx * nty * nseg;
     if (blocks > ((int64_t)1 << 30)) return hipErrorInvalidValue;
     if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)K * 2 * nt * W * sizeof(float);
+    // two LDS buffers per stage, four for the paired form
+    const size_t lds = (size_t)K * (PAIR ? 4 : 2) * nt * W * sizeof(float);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    auto kern = star3d_stream<R, K, VEC, WL, prefetch3<STAR_R, K, VEC, WL>(), AL>;
+    auto kern = star3d_stream<R, K, VEC, WL, prefetch3<STAR_R, K, VEC, WL>(), AL, PAIR>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -65,6 +66,15 @@ hipError_t launch_kv(const Star3DArgs &a, hipStream_t stream) {
     if constexpr (K > max_k3d(STAR_R)) {
         return hipErrorInvalidValue;
     } else {
+        if constexpr (K == 1) {
+            if (a.pair && a.vec == 4 && a.wl == 64)
+                return a.aligned ? launch_k3<K, 4, 64, true, true>(a, stream)
+                                 : launch_k3<K, 4, 64, false, true>(a, stream);
+            if (a.pair && a.vec == 4 && a.wl == 32)
+                return a.aligned ? launch_k3<K, 4, 32, true, true>(a, stream)
+                                 : launch_k3<K, 4, 32, false, true>(a, stream);
+        }
+        if (a.pair) return hipErrorInvalidValue;  // single-step, 4 cells per lane only
         if (a.vec == 4 && a.wl == 64)
             return a.aligned ? launch_k3<K, 4, 64, true>(a, stream) : launch_k3<K, 4, 64, false>(a, stream);
         if (a.vec == 4 && a.wl == 32)

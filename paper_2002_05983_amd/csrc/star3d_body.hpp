@@ -67,16 +67,24 @@ __device__ __forceinline__ void lds_read_row(const float *row, int lr, float (&v
 // whose columns, rows and planes stay inside the grid at every stage
 // (star3d_interior): no clamp is ever applied and the border code is left
 // out; for such a tile it computes the same bits as the general form.
-template <int R, int K, int VEC, int WL, int D, bool ALIGNED, bool EDGE = true>
+// PAIR (single-step passes only): two planes per barrier -- both centre
+// rows go to LDS (four buffers), then both planes are computed -- which
+// halves the barriers and the per-plane synchronisation; the same bits.
+template <int R, int K, int VEC, int WL, int D, bool ALIGNED, bool EDGE = true, bool PAIR = false>
 __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float *__restrict__ dst,
                                             int nx, int ny, int nz, int hx, int tx, int strip,
                                             int ytile, int zseg, int lz, const Coefs &cf) {
+    static_assert(!PAIR || K == 1, "two planes per barrier: single-step passes only");
     constexpr int P = 2 * R + 1;      // planes a stage keeps: its z-window
-    constexpr int NQ = P + D;         // input ring: window plus D planes in flight
+    // input ring: window plus D planes in flight (plus one in the paired
+    // form, whose second load would otherwise overwrite the first plane's
+    // oldest window plane)
+    constexpr int NQ = P + D + (PAIR ? 1 : 0);
     constexpr int DIST = D;           // prefetch distance in planes
     // Unrolled planes per loop trip: every ring index must be compile-time,
-    // so the trip covers a whole number of turns of each ring.
-    constexpr int U = (K == 1) ? NQ : NQ * P / gcd_i(NQ, P);
+    // so the trip covers a whole number of turns of each ring (and, paired,
+    // a whole number of pairs).
+    constexpr int U = PAIR ? (NQ % 2 == 0 ? NQ : 2 * NQ) : (K == 1) ? NQ : NQ * P / gcd_i(NQ, P);
     constexpr int RPW = 64 / WL;      // tile rows per wavefront
     constexpr int W = WL * VEC;       // columns per tile row
     constexpr int ROWF = W;           // floats per LDS row
@@ -235,6 +243,31 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
         load_plane(zstart + decltype(phc)::value, q0[decltype(phc)::value]);
     });
 
+    // The output row of plane r (stage K), masked to the tile and grid.
+    auto store_row = [&](int r, const float (&res)[VEC]) STAR_INLINE {
+        // one descriptor per plane (wave-uniform); the row goes into the
+        // per-lane offset
+        const bool ok_row = row_out && r >= z0 && r < z1;
+        const auto rs = buffer_rsrc(dst + (size_t)clampi(r, nz) * plane, plane_bytes);
+        const int rowoff = yc * nx;
+        if constexpr (ALIGNED) {
+#pragma unroll
+            for (int c = 0; c < VEC / 4; ++c) {
+                const int cc = col0 + 4 * c;
+                const bool ok = ok_row && cc >= out_lo && cc + 4 <= out_hi;
+                buffer_store4(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[4 * c], res[4 * c + 1],
+                              res[4 * c + 2], res[4 * c + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int cc = col0 + e;
+                const bool ok = ok_row && cc >= out_lo && cc < out_hi;
+                buffer_store1(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[e]);
+            }
+        }
+    };
+
     auto step_plane = [&](auto phc, int n) STAR_INLINE {
         constexpr int PH = decltype(phc)::value % NQ;  // slot in the input ring
         constexpr int PS = decltype(phc)::value % P;   // slot in the stage windows
@@ -290,39 +323,66 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
                         }
                     }
                 } else {
-                    // one descriptor per plane (wave-uniform); the row goes
-                    // into the per-lane offset
-                    const bool ok_row = row_out && r >= z0 && r < z1;
-                    const auto rs = buffer_rsrc(dst + (size_t)clampi(r, nz) * plane, plane_bytes);
-                    const int rowoff = yc * nx;
-                    if constexpr (ALIGNED) {
-#pragma unroll
-                        for (int c = 0; c < VEC / 4; ++c) {
-                            const int cc = col0 + 4 * c;
-                            const bool ok = ok_row && cc >= out_lo && cc + 4 <= out_hi;
-                            buffer_store4(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[4 * c],
-                                          res[4 * c + 1], res[4 * c + 2], res[4 * c + 3]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            const int cc = col0 + e;
-                            const bool ok = ok_row && cc >= out_lo && cc < out_hi;
-                            buffer_store1(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[e]);
-                        }
-                    }
+                    store_row(r, res);
                 }
             });
         }
     };
 
+    // Paired form: iterations n (even) and n+1 share one barrier; their
+    // centre rows go to LDS buffers b and b+1 (b alternates 0, 2), whose
+    // previous readers finished before the last pair's barrier.
+    auto step_pair = [&](auto phc, int n) STAR_INLINE {
+        constexpr int PH0 = decltype(phc)::value % NQ;
+        constexpr int PH1 = (decltype(phc)::value + 1) % NQ;
+        const int zl = zstart + n;
+        const int b = n & 2;
+        load_plane(zl + DIST, q0[(PH0 + DIST) % NQ]);
+        load_plane(zl + 1 + DIST, q0[(PH1 + DIST) % NQ]);
+        if constexpr (ALIGNED) {
+            xfix(q0[PH0]);
+            xfix(q0[PH1]);
+        }
+        lds_write_row<VEC, WL>(lds_row(0, b, trow), lr, q0[(PH0 - R + NQ) % NQ]);
+        lds_write_row<VEC, WL>(lds_row(0, b + 1, trow), lr, q0[(PH1 - R + NQ) % NQ]);
+        __syncthreads();
+        if (load_only) return;
+        if (n >= 2 * R) {  // the first plane an output needs comes 2R planes in
+            float res[VEC];
+            cells(std::integral_constant<int, NQ>{}, std::integral_constant<int, (PH0 - R + NQ) % NQ>{},
+                  q0, 0, b, res);
+            store_row(zl - R, res);
+        }
+        // one plane at a time: interleaving the two would raise the
+        // register pressure past the 128-VGPR budget
+        __builtin_amdgcn_sched_barrier(0);
+        if (n + 1 >= 2 * R && n + 1 < niter) {
+            float res[VEC];
+            cells(std::integral_constant<int, NQ>{}, std::integral_constant<int, (PH1 - R + NQ) % NQ>{},
+                  q0, 0, b + 1, res);
+            store_row(zl + 1 - R, res);
+        }
+    };
+
     int n0 = 0;
-    for (; n0 + U <= niter; n0 += U) {
-        static_for<0, U>([&](auto phc) STAR_INLINE { step_plane(phc, n0 + decltype(phc)::value); });
+    if constexpr (PAIR) {
+        for (; n0 + U <= niter; n0 += U) {
+            static_for<0, U / 2>([&](auto pc) STAR_INLINE {
+                step_pair(std::integral_constant<int, 2 * decltype(pc)::value>{}, n0 + 2 * decltype(pc)::value);
+            });
+        }
+        static_for<0, U / 2>([&](auto pc) STAR_INLINE {
+            if (n0 + 2 * decltype(pc)::value < niter)
+                step_pair(std::integral_constant<int, 2 * decltype(pc)::value>{}, n0 + 2 * decltype(pc)::value);
+        });
+    } else {
+        for (; n0 + U <= niter; n0 += U) {
+            static_for<0, U>([&](auto phc) STAR_INLINE { step_plane(phc, n0 + decltype(phc)::value); });
+        }
+        static_for<0, U>([&](auto phc) STAR_INLINE {
+            if (n0 + decltype(phc)::value < niter) step_plane(phc, n0 + decltype(phc)::value);
+        });
     }
-    static_for<0, U>([&](auto phc) STAR_INLINE {
-        if (n0 + decltype(phc)::value < niter) step_plane(phc, n0 + decltype(phc)::value);
-    });
 }
 
 // True when a tile needs no clamp at any stage: its columns xs .. xs+W-1,

@@ -79,6 +79,8 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                             snprintf(buf, sizeof buf, "k=%d,wl=%d,vec=%d,lz=%d,nw=%d", K, wl, vec, lz,
                                      nw);
                             out.push_back(buf);
+                            if (K == 1 && vec == 4 && !lowp)  // two planes per barrier
+                                out.push_back(std::string(buf) + ",pair=1");
                         }
                     }
                 }

@@ -124,6 +124,12 @@ def test_s3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
                                 tune=f"k={K},nw={nw},lz={lz},wl={wl}")
             assert "variant=s3d" in desc, desc
             assert_bitwise(got, cache[steps], f"s3d {shape} r{radius} [{desc}]")
+        if K == 1:  # two planes per barrier; odd and even plane counts per segment
+            for nw, lz, wl in ((16, 5, 64), (16, 7, 32), (radius + 1, 4, 32), (16, 64, 32)):
+                got, desc = gpu_run(torch, st, f, radius, c, 3,
+                                    tune=f"k=1,nw={nw},lz={lz},wl={wl},pair=1")
+                assert "pair=1" in desc, desc
+                assert_bitwise(got, cache[3], f"s3d pair {shape} r{radius} [{desc}]")
         if K == 1 and shape[2] % 4 == 0 and 256 < shape[2] <= 512 and radius <= 2:
             got, desc = gpu_run(torch, st, f, radius, c, 3, tune="k=1,vec=8,wl=64,lz=7")
             assert "vec=8" in desc
@@ -152,7 +158,8 @@ def test_3d_high_radius_matches_oracle_bitwise(torch, st, oracle_mod, radius, sh
     c = synth.coefficients(800 + radius, 3, radius)
     f = synth.grid_uniform(900 + radius, shape)
     want = {s: oracle_mod.star_run_f32(f, c, radius, s) for s in (1, 4)}
-    tunes = [None, "naive", "k=1,wl=32,nw=16,lz=7", "k=1,wl=32,nw=12,lz=64"]
+    tunes = [None, "naive", "k=1,wl=32,nw=16,lz=7", "k=1,wl=32,nw=12,lz=64",
+             "k=1,wl=32,nw=16,lz=9,pair=1"]
     if radius < 8:
         tunes.append("k=1,wl=64,nw=16,lz=5")  # 16 rows hold 2R halo rows up to R = 7
     for tune in tunes:
