@@ -110,9 +110,16 @@ STENCIL_API int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims
  *            step every anchor_m steps re-derives the scales).
  *   anchor_m for the low-precision forms: steps per window (>= 1); ignored
  *            for F32.
- *   tune     NULL for automatic selection, or a configuration string such as
- *            "naive", "k=4,ly=256" (2D) or "k=2,tx=120,ty=24,lz=64" (3D);
- *            unknown keys or infeasible values give EINVAL.
+ *   tune     NULL for automatic selection, or a configuration string of
+ *            comma-separated items: "naive" (one thread per cell, one step
+ *            per launch); 2D "k=" (fused steps, K*R <= 16, at most 8) and
+ *            "ly=" (rows per segment); 3D "k=" (4/2/1 for R = 1/2/3..8),
+ *            "wl=" (lanes per tile row, 32 or 64), "vec=" (cells per lane,
+ *            4, or 8 for wl=64, k=1, R <= 2, aligned rows), "nw=" (waves per
+ *            workgroup, <= 16), "lz=" (planes per segment) and "pair=1" (two
+ *            planes per barrier, k=1, vec=4).  E.g. "k=4,ly=256" (2D),
+ *            "k=2,wl=32,nw=16,lz=64" (3D).  Unknown keys or infeasible
+ *            values give EINVAL.
  */
 STENCIL_API int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
                     const float *coeffs, int ncoeffs, int boundary, int storage,
