@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "liboracle_star.so")
 def build(verbose: bool = False) -> str:
     cc = os.environ.get("CC", "gcc")
     tmp = OUT + ".tmp"
-    cmd = [cc, "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+    cmd = [cc, "-O3", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))

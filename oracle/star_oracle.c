@@ -68,61 +68,112 @@ static int check_args(int ndim, const int64_t *dims, int rad, int ncoef,
     return 0;
 }
 
-/* One step of Eq. (1) with the clamp boundary, in double precision. */
-static void step_f64(int ndim, int64_t nx, int64_t ny, int64_t nz, int rad,
+/*
+ * One step of Eq. (1) with the clamp boundary, in double precision.
+ *
+ * The sum is evaluated one grid row at a time: every cell of the row starts
+ * from the centre product c_C*f(p), then each neighbour term is added in the
+ * coefficient order (for i = 1..rad: W, E, S, N[, B, A]).  Each cell thus
+ * sees exactly the operations and order of the per-cell sum; only the loop
+ * over the cells of a row is moved inside the loop over terms, so that the
+ * compiler can vectorise it.  The x-neighbours are read from a copy of the
+ * row with `rad` border values repeated at each end (the clamp along x); the
+ * y- and z-neighbours are whole rows whose row index is clamped.
+ */
+static int step_f64(int ndim, int64_t nx, int64_t ny, int64_t nz, int rad,
                      const double *c, const double *src, double *dst, int nthreads)
 {
-#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
-    for (int64_t z = 0; z < nz; ++z) {
-        for (int64_t y = 0; y < ny; ++y) {
-            for (int64_t x = 0; x < nx; ++x) {
-#define F(xx, yy, zz) src[(xx) + nx * ((yy) + ny * (zz))]
-                double acc = c[0] * F(x, y, z);
+    int status = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        double *padded = (double *)malloc((size_t)(nx + 2 * rad) * sizeof(double));
+        if (!padded) {
+#pragma omp atomic write
+            status = -2;
+        }
+#pragma omp for collapse(2) schedule(static)
+        for (int64_t z = 0; z < nz; ++z) {
+            for (int64_t y = 0; y < ny; ++y) {
+                if (!padded) continue;
+#define ROW(yy, zz) (src + nx * ((yy) + ny * (zz)))
+                const double *row = ROW(y, z);
+                double *out = dst + nx * (y + ny * z);
+                for (int64_t x = -rad; x < nx + rad; ++x)
+                    padded[x + rad] = row[clamp_index(x, nx)];
+                const double *f = padded + rad;   /* f[x - i] .. f[x + i] valid */
+                for (int64_t x = 0; x < nx; ++x) out[x] = c[0] * f[x];
                 int k = 1;
                 for (int i = 1; i <= rad; ++i) {
-                    acc += c[k++] * F(clamp_index(x - i, nx), y, z);   /* W */
-                    acc += c[k++] * F(clamp_index(x + i, nx), y, z);   /* E */
-                    acc += c[k++] * F(x, clamp_index(y - i, ny), z);   /* S */
-                    acc += c[k++] * F(x, clamp_index(y + i, ny), z);   /* N */
+                    const double cw = c[k++], ce = c[k++], cs = c[k++], cn = c[k++];
+                    const double *south = ROW(clamp_index(y - i, ny), z);
+                    const double *north = ROW(clamp_index(y + i, ny), z);
+                    for (int64_t x = 0; x < nx; ++x) out[x] += cw * f[x - i];      /* W */
+                    for (int64_t x = 0; x < nx; ++x) out[x] += ce * f[x + i];      /* E */
+                    for (int64_t x = 0; x < nx; ++x) out[x] += cs * south[x];     /* S */
+                    for (int64_t x = 0; x < nx; ++x) out[x] += cn * north[x];     /* N */
                     if (ndim == 3) {
-                        acc += c[k++] * F(x, y, clamp_index(z - i, nz)); /* B */
-                        acc += c[k++] * F(x, y, clamp_index(z + i, nz)); /* A */
+                        const double cb = c[k++], ca = c[k++];
+                        const double *below = ROW(y, clamp_index(z - i, nz));
+                        const double *above = ROW(y, clamp_index(z + i, nz));
+                        for (int64_t x = 0; x < nx; ++x) out[x] += cb * below[x];  /* B */
+                        for (int64_t x = 0; x < nx; ++x) out[x] += ca * above[x];  /* A */
                     }
                 }
-                dst[x + nx * (y + ny * z)] = acc;
-#undef F
+#undef ROW
             }
         }
+        free(padded);
     }
+    return status;
 }
 
-/* The same step in single precision, centre product then one fmaf per
- * neighbour in coefficient order. */
-static void step_f32(int ndim, int64_t nx, int64_t ny, int64_t nz, int rad,
-                     const float *c, const float *src, float *dst, int nthreads)
+/* The same step in single precision: the centre product, then one fmaf per
+ * neighbour in coefficient order (same row-at-a-time evaluation). */
+static int step_f32(int ndim, int64_t nx, int64_t ny, int64_t nz, int rad,
+                    const float *c, const float *src, float *dst, int nthreads)
 {
-#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
-    for (int64_t z = 0; z < nz; ++z) {
-        for (int64_t y = 0; y < ny; ++y) {
-            for (int64_t x = 0; x < nx; ++x) {
-#define F(xx, yy, zz) src[(xx) + nx * ((yy) + ny * (zz))]
-                float acc = c[0] * F(x, y, z);
+    int status = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        float *padded = (float *)malloc((size_t)(nx + 2 * rad) * sizeof(float));
+        if (!padded) {
+#pragma omp atomic write
+            status = -2;
+        }
+#pragma omp for collapse(2) schedule(static)
+        for (int64_t z = 0; z < nz; ++z) {
+            for (int64_t y = 0; y < ny; ++y) {
+                if (!padded) continue;
+#define ROW(yy, zz) (src + nx * ((yy) + ny * (zz)))
+                const float *row = ROW(y, z);
+                float *out = dst + nx * (y + ny * z);
+                for (int64_t x = -rad; x < nx + rad; ++x)
+                    padded[x + rad] = row[clamp_index(x, nx)];
+                const float *f = padded + rad;
+                for (int64_t x = 0; x < nx; ++x) out[x] = c[0] * f[x];
                 int k = 1;
                 for (int i = 1; i <= rad; ++i) {
-                    acc = fmaf(c[k], F(clamp_index(x - i, nx), y, z), acc); ++k;
-                    acc = fmaf(c[k], F(clamp_index(x + i, nx), y, z), acc); ++k;
-                    acc = fmaf(c[k], F(x, clamp_index(y - i, ny), z), acc); ++k;
-                    acc = fmaf(c[k], F(x, clamp_index(y + i, ny), z), acc); ++k;
+                    const float cw = c[k++], ce = c[k++], cs = c[k++], cn = c[k++];
+                    const float *south = ROW(clamp_index(y - i, ny), z);
+                    const float *north = ROW(clamp_index(y + i, ny), z);
+                    for (int64_t x = 0; x < nx; ++x) out[x] = fmaf(cw, f[x - i], out[x]);
+                    for (int64_t x = 0; x < nx; ++x) out[x] = fmaf(ce, f[x + i], out[x]);
+                    for (int64_t x = 0; x < nx; ++x) out[x] = fmaf(cs, south[x], out[x]);
+                    for (int64_t x = 0; x < nx; ++x) out[x] = fmaf(cn, north[x], out[x]);
                     if (ndim == 3) {
-                        acc = fmaf(c[k], F(x, y, clamp_index(z - i, nz)), acc); ++k;
-                        acc = fmaf(c[k], F(x, y, clamp_index(z + i, nz)), acc); ++k;
+                        const float cb = c[k++], ca = c[k++];
+                        const float *below = ROW(y, clamp_index(z - i, nz));
+                        const float *above = ROW(y, clamp_index(z + i, nz));
+                        for (int64_t x = 0; x < nx; ++x) out[x] = fmaf(cb, below[x], out[x]);
+                        for (int64_t x = 0; x < nx; ++x) out[x] = fmaf(ca, above[x], out[x]);
                     }
                 }
-                dst[x + nx * (y + ny * z)] = acc;
-#undef F
+#undef ROW
             }
         }
+        free(padded);
     }
+    return status;
 }
 
 /*
@@ -144,7 +195,10 @@ int oracle_star_run_f64(int ndim, const int64_t *dims, int rad,
     if (!a || !b) { free(a); free(b); return -2; }
     memcpy(a, f0, n * sizeof(double));
     for (int64_t t = 0; t < steps; ++t) {
-        step_f64(ndim, nx, ny, nz, rad, coef, a, b, nthreads);
+        if (step_f64(ndim, nx, ny, nz, rad, coef, a, b, nthreads)) {
+            free(a); free(b);
+            return -2;
+        }
         double *tmp = a; a = b; b = tmp;
     }
     memcpy(out, a, n * sizeof(double));
@@ -168,7 +222,10 @@ int oracle_star_run_f32(int ndim, const int64_t *dims, int rad,
     if (!a || !b) { free(a); free(b); return -2; }
     memcpy(a, f0, n * sizeof(float));
     for (int64_t t = 0; t < steps; ++t) {
-        step_f32(ndim, nx, ny, nz, rad, coef, a, b, nthreads);
+        if (step_f32(ndim, nx, ny, nz, rad, coef, a, b, nthreads)) {
+            free(a); free(b);
+            return -2;
+        }
         float *tmp = a; a = b; b = tmp;
     }
     memcpy(out, a, n * sizeof(float));
