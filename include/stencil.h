@@ -113,7 +113,8 @@ STENCIL_API int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims
  *   tune     NULL for automatic selection, or a configuration string of
  *            comma-separated items: "naive" (one thread per cell, one step
  *            per launch); 2D "k=" (fused steps, K*R <= 16, at most 8) and
- *            "ly=" (rows per segment); 3D "k=" (4/2/1 for R = 1/2/3..8),
+ *            "ly=" (rows per segment); 3D "k=" (at most 4 for R = 1, 3 for
+ *            R = 2, 3, 2 for R = 4..6, 1 for R = 7, 8),
  *            "wl=" (lanes per tile row, 32 or 64), "vec=" (cells per lane,
  *            4, or 8 for wl=64, k=1, R <= 2, aligned rows), "nw=" (waves per
  *            workgroup, <= 16), "lz=" (planes per segment) and "pair=1" (two
@@ -261,6 +262,9 @@ STENCIL_API int stencil_plan_describe(stencil_plan_t plan, char *buf, size_t len
  *   x    device array of n floats; ref device array of n doubles (may be
  *        NULL, then out[0] = out[1] = 0).
  *   out  HOST array of 3 doubles; the call synchronises `stream`.
+ * A NaN in x or ref, or an infinity in x where ref is finite, makes out[0]
+ * NaN or infinite (never silently skipped); a NaN in ref also makes out[1]
+ * NaN; the sum carries NaN and infinities as FP64 addition does.
  * Errors: EINVAL, ENOMEM, EDEVICE.
  */
 STENCIL_API int stencil_reduce_f64(const float *x, const double *ref, int64_t n, double out[3], void *stream);

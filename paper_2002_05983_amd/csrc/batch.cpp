@@ -684,7 +684,10 @@ int batch_create(stencil_batch_t *out, int n, const stencil_plan_t *plans, const
     std::map<std::tuple<int, int, int, int>, int> index;
     for (int g = 0; g < n; ++g) {
         const stencil_plan_s *p = plans[g];
-        const bool wide_plane = p->ndim == 3 && p->nx * p->ny * 4 >= ((int64_t)1 << 31);
+        // rows (2D) and planes (3D) are addressed through buffer descriptors
+        // whose byte sizes must stay below 2^31
+        const bool wide_plane = (p->ndim == 3 && p->nx * p->ny * 4 >= ((int64_t)1 << 31)) ||
+                                (p->ndim == 2 && p->nx * 4 >= ((int64_t)1 << 31));
         const bool high_radius = p->radius > 4;  // work-list kernels are built for R <= 4
         if (steps[g] == 0 || p->storage != STENCIL_F32 || wide_plane || high_radius) {
             b->own.push_back(g);

@@ -56,7 +56,7 @@ struct Star3DArgs {
 };
 // Largest K built per radius: the tile keeps >= 8 output rows of 16 for
 // R = 1 and every build stays within 128 VGPRs without spilling.
-constexpr int max_k3d(int R) { return R == 1 ? 4 : R == 2 ? 2 : 1; }
+constexpr int max_k3d(int R) { return R == 1 ? 4 : R <= 3 ? 3 : R <= 6 ? 2 : 1; }
 // Widest row: 512 columns (vec 8) for aligned single-step passes of R <= 2.
 constexpr bool vec8_ok(int R, int K, bool aligned) { return K == 1 && R <= 2 && aligned; }
 

@@ -42,6 +42,8 @@ static hipError_t launch_one(const float *src, float *dst, int nx, int ny, int n
                              const Coefs &cf, hipStream_t stream) {
     const int64_t n = (int64_t)nx * ny * nz;
     const int64_t blocks = (n + 255) / 256;
+    // the dispatch's work-item count is 32-bit
+    if (blocks * 256 > (int64_t)0xFFFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL((star_naive<NDIM, R>), dim3((unsigned)blocks), dim3(256), 0, stream, src,
                        dst, nx, ny, nz, n, cf);
     return hipGetLastError();

@@ -159,6 +159,10 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         }
     }
     if (p->variant == STAR_S2D) {
+        // rows are addressed through one buffer descriptor of nx*4 bytes,
+        // whose masked lanes use the offset 2^31
+        if (p->nx * 4 >= ((int64_t)1 << 31))
+            return star_set_error(STENCIL_EUNSUPPORTED, "2D rows must stay below 2^31 bytes");
         if (p->K < 1 || p->K > max_k2d(R))
             return star_set_error(STENCIL_EINVAL, "2D k must be in 1..16/R (at most 8)");
         if (p->ly == 0) p->ly = default_ly(p, p->K);
@@ -179,7 +183,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             if (p->s3_lz == 0) p->s3_lz = 256;  // z-segments of whole 64^3 storage tiles
         }
         if (p->K < 1 || p->K > max_k3d(R))
-            return star_set_error(STENCIL_EINVAL, "3D k must be 1..4 for R = 1, 1..2 for R = 2, 1 above");
+            return star_set_error(STENCIL_EINVAL, "3D k must be 1..4 for R = 1, 1..3 for R = 2, 3, 1..2 for R = 4..6, 1 above");
         if (p->s3_lanes != 64 && p->s3_lanes != 32)
             return star_set_error(STENCIL_EINVAL, "3D wl must be 64 or 32");
         const int rows = p->s3_rows * (64 / p->s3_lanes);

@@ -5,7 +5,10 @@
 // against an FP64 reference, and the sum of the field (conserved when the
 // coefficients sum to 1 and no cell is clamped away; used as a diagnostic).
 // The grid size and the reduction tree are fixed, so the sum is bitwise
-// reproducible from run to run.
+// reproducible from run to run.  The maxima propagate NaN: a NaN (or an
+// infinity, whose difference from a finite reference is infinite and from
+// an infinite one NaN) anywhere in x or ref shows in the result instead of
+// being skipped, as a plain fmax would.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -19,6 +22,9 @@ namespace {
 constexpr int kBlocks = 1024;
 constexpr int kThreads = 256;
 
+// max(a, b) that returns NaN when either operand is NaN.
+__device__ __forceinline__ double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
+
 __global__ __launch_bounds__(kThreads) void reduce_partials(const float *__restrict__ x,
                                                             const double *__restrict__ ref,
                                                             int64_t n, double *__restrict__ part) {
@@ -29,8 +35,8 @@ __global__ __launch_bounds__(kThreads) void reduce_partials(const float *__restr
         sm += xv;
         if (ref) {
             const double rv = ref[i];
-            md = fmax(md, fabs(xv - rv));
-            mr = fmax(mr, fabs(rv));
+            md = max_nan(md, fabs(xv - rv));
+            mr = max_nan(mr, fabs(rv));
         }
     }
     __shared__ double s[3][kThreads];
@@ -40,8 +46,8 @@ __global__ __launch_bounds__(kThreads) void reduce_partials(const float *__restr
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + w]);
-            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[0][threadIdx.x] = max_nan(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = max_nan(s[1][threadIdx.x], s[1][threadIdx.x + w]);
             s[2][threadIdx.x] = s[2][threadIdx.x] + s[2][threadIdx.x + w];
         }
         __syncthreads();
@@ -58,8 +64,8 @@ __global__ __launch_bounds__(kThreads) void reduce_final(const double *__restric
     __shared__ double s[3][kThreads];
     double md = 0.0, mr = 0.0, sm = 0.0;
     for (int i = threadIdx.x; i < np; i += kThreads) {
-        md = fmax(md, part[3 * i + 0]);
-        mr = fmax(mr, part[3 * i + 1]);
+        md = max_nan(md, part[3 * i + 0]);
+        mr = max_nan(mr, part[3 * i + 1]);
         sm += part[3 * i + 2];
     }
     s[0][threadIdx.x] = md;
@@ -68,8 +74,8 @@ __global__ __launch_bounds__(kThreads) void reduce_final(const double *__restric
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + w]);
-            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[0][threadIdx.x] = max_nan(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = max_nan(s[1][threadIdx.x], s[1][threadIdx.x + w]);
             s[2][threadIdx.x] = s[2][threadIdx.x] + s[2][threadIdx.x + w];
         }
         __syncthreads();

@@ -38,6 +38,8 @@ hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
     const int nsegs = (a.ny + a.ly - 1) / a.ly;
     const int64_t nwaves = (int64_t)nstrips * nsegs;
     if (nwaves > (int64_t)1 << 30) return hipErrorInvalidValue;
+    // one row is one buffer descriptor: its byte size and masked offsets stay below 2^31
+    if ((int64_t)a.nx * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
     hipLaunchKernelGGL((star2d_stream<STAR_R, K, prefetch_rows<STAR_R, K>(), AL>), dim3(blocks), dim3(256), 0, stream, a.src,
                        a.dst, a.nx, a.ny, a.ly, nstrips, (int)nwaves, a.cf);

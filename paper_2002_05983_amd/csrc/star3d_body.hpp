@@ -76,15 +76,21 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
                                             int ytile, int zseg, int lz, const Coefs &cf) {
     static_assert(!PAIR || K == 1, "two planes per barrier: single-step passes only");
     constexpr int P = 2 * R + 1;      // planes a stage keeps: its z-window
-    // input ring: window plus D planes in flight (plus one in the paired
-    // form, whose second load would otherwise overwrite the first plane's
-    // oldest window plane)
-    constexpr int NQ = P + D + (PAIR ? 1 : 0);
+    // Single-step passes load straight into an input ring of the window plus
+    // D planes in flight (plus one in the paired form, whose second load
+    // would otherwise overwrite the first plane's oldest window plane).
+    // Passes of K > 1 steps keep the input ring at the window (P planes) and
+    // land their loads in a separate staging ring of D planes, moved into
+    // the window when consumed: every ring then turns with a period dividing
+    // lcm(P, D), which keeps the unrolled loop one or two windows long
+    // whatever D is.
+    constexpr bool STAGED = K > 1;
+    constexpr int NQ = STAGED ? P : P + D + (PAIR ? 1 : 0);
     constexpr int DIST = D;           // prefetch distance in planes
     // Unrolled planes per loop trip: every ring index must be compile-time,
     // so the trip covers a whole number of turns of each ring (and, paired,
     // a whole number of pairs).
-    constexpr int U = PAIR ? (NQ % 2 == 0 ? NQ : 2 * NQ) : (K == 1) ? NQ : NQ * P / gcd_i(NQ, P);
+    constexpr int U = PAIR ? (NQ % 2 == 0 ? NQ : 2 * NQ) : (K == 1) ? NQ : P * D / gcd_i(P, D);
     constexpr int RPW = 64 / WL;      // tile rows per wavefront
     constexpr int W = WL * VEC;       // columns per tile row
     constexpr int ROWF = W;           // floats per LDS row
@@ -100,9 +106,15 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     const int trow = w * RPW + lane / WL;  // this lane's tile row
     const int y = ty0 - K * R + trow;      // and grid row
     const int yc = clampi(y, ny);
-    // rows 0..R-1 and nt-R..nt-1 only feed stage 1; a wavefront made of
-    // such rows only loads
-    const bool load_only = (w * RPW + RPW - 1 < R) || (w * RPW >= nt - R);
+    // Stage s (1-based) is needed on tile rows s*R .. nt-1-s*R (the rows of
+    // stage s+1's y-window, or the output rows for s = K); a wavefront
+    // computes a stage only when one of its rows is among them.  Rows
+    // 0..R-1 and nt-R..nt-1 only feed stage 1: a wavefront made of such
+    // rows only loads.
+    auto computes = [&](int s) STAR_INLINE {
+        return w * RPW + RPW - 1 >= s * R && w * RPW < nt - s * R;
+    };
+    const bool load_only = !computes(1);
     const int xs = strip * tx - hx;   // first column held by lane 0 of a row
     const int col0 = xs + lr * VEC;
     const int z0 = zseg * lz;
@@ -227,6 +239,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
     };
 
     float q0[NQ][VEC];
+    float stg[STAGED ? D : 1][VEC];
     float q[K > 1 ? K - 1 : 1][P][VEC];
 #pragma unroll
     for (int s = 0; s < (K > 1 ? K - 1 : 1); ++s)
@@ -240,7 +253,10 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
         for (int e = 0; e < VEC; ++e) q0[p][e] = 0.0f;
 
     static_for<0, DIST>([&](auto phc) STAR_INLINE {
-        load_plane(zstart + decltype(phc)::value, q0[decltype(phc)::value]);
+        if constexpr (STAGED)
+            load_plane(zstart + decltype(phc)::value, stg[decltype(phc)::value]);
+        else
+            load_plane(zstart + decltype(phc)::value, q0[decltype(phc)::value]);
     });
 
     // The output row of plane r (stage K), masked to the tile and grid.
@@ -273,25 +289,33 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
         constexpr int PS = decltype(phc)::value % P;   // slot in the stage windows
         const int zl = zstart + n;  // plane entering stage 1
         const int b = n & 1;        // LDS buffer of this iteration
-        load_plane(zl + DIST, q0[(PH + DIST) % NQ]);
+        if constexpr (STAGED) {
+            // plane zl arrived in staging slot n % D; move it into the window
+            // and reuse the slot for plane zl + D
+            constexpr int PD = decltype(phc)::value % D;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q0[PH][e] = stg[PD][e];
+            load_plane(zl + DIST, stg[PD]);
+        } else {
+            load_plane(zl + DIST, q0[(PH + DIST) % NQ]);
+        }
         if constexpr (ALIGNED) xfix(q0[PH]);
         // centre planes of every stage into LDS
         lds_write_row<VEC, WL>(lds_row(0, b, trow), lr, q0[(PH - R + NQ) % NQ]);
-        if (!load_only) {
-            static_for<2, K + 1>([&](auto sc) STAR_INLINE {
-                constexpr int S = decltype(sc)::value;
-                if (n < 2 * S * R) return;  // stage S not started (below)
-                lds_write_row<VEC, WL>(lds_row(S - 1, b, trow), lr, q[S - 2][(PS - R + P) % P]);
-            });
-        }
+        static_for<2, K + 1>([&](auto sc) STAR_INLINE {
+            constexpr int S = decltype(sc)::value;
+            if (n < 2 * S * R || !computes(S - 1)) return;  // stage S not started (below)
+            lds_write_row<VEC, WL>(lds_row(S - 1, b, trow), lr, q[S - 2][(PS - R + P) % P]);
+        });
         __syncthreads();
         if (!load_only) {
             static_for<1, K + 1>([&](auto sc) STAR_INLINE {
                 constexpr int S = decltype(sc)::value;
                 // Stage S first produces a plane that an output depends on at
                 // iteration 2*S*R (workgroup-uniform); before that nothing
-                // reads what it would produce.
-                if (n < 2 * S * R) return;
+                // reads what it would produce.  A wavefront none of whose rows
+                // stage S needs skips it.
+                if (n < 2 * S * R || !computes(S)) return;
                 const int r = zl - S * R;  // plane produced by stage S
                 float res[VEC];
                 if constexpr (S == 1)
@@ -401,12 +425,13 @@ __device__ __forceinline__ bool star3d_interior(int nx, int ny, int nz, int hx, 
 }
 
 // Prefetch depth (planes) per configuration, sized so that a 1024-thread
-// workgroup stays within 128 VGPRs per lane: deep for K = 1 (memory bound),
-// one window (D = P) for K > 1 so the unroll stays 2P.
+// workgroup stays within 128 VGPRs per lane: deep for K = 1 (memory bound);
+// for K > 1 (VALU bound) a staging ring of two planes, one at radius >= 3
+// where K windows of 2R+1 planes fill the budget.
 template <int R, int K, int VEC, int WL>
 constexpr int prefetch3() {
     constexpr int P = 2 * R + 1;
-    if constexpr (K > 1) return P;
+    if constexpr (K > 1) return R >= 3 ? 1 : 2;
     if constexpr (R > 4) return 1;  // high radius: the z-window alone nears the budget
     if constexpr (VEC == 4 && WL == 32) return P + 3 > 12 ? 3 : 12 - P;  // two rows per wave
     if constexpr (VEC == 4) return P + 4 > 12 ? 4 : 12 - P;  // ring of max(12, P + 4) planes

@@ -89,18 +89,23 @@ def test_plan_rejects_invalid_arguments(lib, case):
 
 
 def test_plan_radius_limits(lib):
-    """Radius 1..8 in 2D and 3D.  In 3D above radius 4 only single-step
-    passes exist (k > 1 is invalid) and low-precision storage is a valid
-    request this build does not support.  Decided before any device call."""
+    """Radius 1..8 in 2D and 3D.  In 3D, K is at most 2 at radius 5, 6
+    and 1 at radius 7, 8 (a larger k is invalid), and low-precision storage
+    is a valid request this build does not support above radius 4.  Decided
+    before any device call."""
     for ndim in (2, 3):
         rc, h = _plan(lib, ndim, [4] * ndim, 9, [0.0] * (1 + 2 * ndim * 9))
         assert rc == -1 and not h.value
-    for radius in (5, 8):
+    for radius, kbad in ((5, 3), (6, 3), (7, 2), (8, 2)):
         c = [0.0] * (1 + 6 * radius)
         rc, h = _plan(lib, 3, [16, 16, 16], radius, c, storage=1, anchor=3)
         assert rc == -4 and not h.value, (radius, rc)
         assert b"radius 1..4" in lib.stencil_last_error()
-        rc, h = _plan(lib, 3, [16, 16, 16], radius, c, tune=b"k=2")
+        rc, h = _plan(lib, 3, [16, 16, 16], radius, c, tune=b"k=%d" % kbad)
+        assert rc == -1 and not h.value, (radius, rc)
+    for radius, kbad in ((1, 5), (2, 4), (3, 4), (4, 3)):
+        c = [0.0] * (1 + 6 * radius)
+        rc, h = _plan(lib, 3, [16, 16, 16], radius, c, tune=b"k=%d" % kbad)
         assert rc == -1 and not h.value, (radius, rc)
 
 
@@ -150,7 +155,11 @@ def test_batch_entry_points_reject_null(lib):
     (3, [512, 64, 64], 2, b"k=1,vec=8,wl=32", False),   # wide rows need 64 lanes
     (3, [510, 64, 64], 1, b"k=1,vec=8,wl=64", False),   # ... and 16-byte rows
     (3, [512, 64, 64], 3, b"k=1,vec=8,wl=64", False),   # ... and R <= 2
-    (3, [64, 64, 64], 2, b"k=3", False),
+    (3, [64, 64, 64], 2, b"k=4", False),
+    (3, [64, 64, 64], 3, b"k=3", True),
+    (3, [64, 64, 64], 4, b"k=2", True),
+    (3, [64, 64, 64], 4, b"k=3", False),
+    (3, [64, 64, 64], 4, b"k=2,nw=16,wl=64", False),    # 16 rows < 2*K*R+1
     (3, [64, 64, 64], 4, b"k=1,nw=4,wl=64", False),     # 4 rows < 2*K*R+1
     (3, [64, 64, 64], 4, b"k=1,nw=5,wl=32", True),
     (3, [64, 64, 64], 1, b"wl=16", False),
@@ -173,5 +182,13 @@ def test_3d_plane_limit_is_checked_before_the_device(lib):
     # 8 x 67108864 cells x 4 B = 2^31 bytes per plane: beyond 32-bit plane offsets
     c = [0.1] * 7
     rc, h = _plan(lib, 3, [67108864, 8, 2], 1, c)
+    assert rc == -4 and not h.value, (rc, lib.stencil_last_error())
+    assert b"2^31" in lib.stencil_last_error()
+
+
+def test_2d_row_limit_is_checked_before_the_device(lib):
+    # 2^29 + 1 columns x 4 B exceed the 2^31-byte row descriptor of the 2D kernels
+    c = [0.2] * 5
+    rc, h = _plan(lib, 2, [(1 << 29) + 1, 2], 1, c)
     assert rc == -4 and not h.value, (rc, lib.stencil_last_error())
     assert b"2^31" in lib.stencil_last_error()

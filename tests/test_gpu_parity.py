@@ -105,7 +105,18 @@ def test_s2d_default_config_vs_fp64(torch, st, oracle_mod, radius):
 # (unaligned), small sides, several y-tiles and z-segments.
 S3D_SHAPES = [(1, 1, 1), (3, 2, 5), (4, 5, 6), (9, 17, 33), (20, 37, 300), (13, 40, 513),
               (7, 33, 600), (30, 50, 64), (6, 3, 257)]
-MAX_K3D = {1: 4, 2: 2, 3: 1, 4: 1}
+MAX_K3D = {1: 4, 2: 3, 3: 3, 4: 2}
+
+
+def s3d_tiles(K, radius):
+    """(nw, lz, wl) tile shapes with at least one output row: 16- and
+    32-row tiles, and the smallest tiles of each row width."""
+    out = []
+    for nw, lz, wl in ((16, 5, 64), (2 * K * radius + 1, 32, 64), (16, 7, 32),
+                       (K * radius + 1, 3, 32)):
+        if nw <= 16 and nw * (64 // wl) > 2 * K * radius:
+            out.append((nw, lz, wl))
+    return out
 
 
 @pytest.mark.parametrize("radius", [1, 2, 3, 4])
@@ -115,8 +126,7 @@ def test_s3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
     f = synth.grid_uniform(800 + radius, shape)
     cache = {}
     for K in range(1, MAX_K3D[radius] + 1):
-        for nw, lz, wl in ((16, 5, 64), (2 * K * radius + 2, 32, 64), (16, 7, 32),
-                           (K * radius + 1, 3, 32)):
+        for nw, lz, wl in s3d_tiles(K, radius):
             steps = 2 * K + 1
             if steps not in cache:
                 cache[steps] = oracle_mod.star_run_f32(f, c, radius, steps)
@@ -157,16 +167,21 @@ def test_3d_high_radius_matches_oracle_bitwise(torch, st, oracle_mod, radius, sh
     wavefront) and 16 rows."""
     c = synth.coefficients(800 + radius, 3, radius)
     f = synth.grid_uniform(900 + radius, shape)
-    want = {s: oracle_mod.star_run_f32(f, c, radius, s) for s in (1, 4)}
+    want = {s: oracle_mod.star_run_f32(f, c, radius, s) for s in (1, 4, 5)}
     tunes = [None, "naive", "k=1,wl=32,nw=16,lz=7", "k=1,wl=32,nw=12,lz=64",
              "k=1,wl=32,nw=16,lz=9,pair=1"]
     if radius < 8:
         tunes.append("k=1,wl=64,nw=16,lz=5")  # 16 rows hold 2R halo rows up to R = 7
+    if radius <= 6:  # two fused steps: 32-row tiles keep 32 - 4R > 0 output rows
+        tunes += ["k=2,wl=32,nw=16,lz=6", "k=2,wl=32,nw=16,lz=64"]
+    got4 = None
     for tune in tunes:
-        for steps in (1, 4):
+        for steps in ((1, 4, 5) if tune and tune.startswith("k=2") else (1, 4)):
             got, desc = gpu_run(torch, st, f, radius, c, steps, tune=tune)
             assert_bitwise(got, want[steps], f"3D {shape} r{radius} {desc}")
-    assert oracle_mod.rel_linf(got, oracle_mod.star_run_f64(f, c, radius, 4)) <= TOL_F64
+            if steps == 4:
+                got4 = got
+    assert oracle_mod.rel_linf(got4, oracle_mod.star_run_f64(f, c, radius, 4)) <= TOL_F64
 
 
 def test_3d_high_radius_autotune(torch, st, oracle_mod):
@@ -179,12 +194,13 @@ def test_3d_high_radius_autotune(torch, st, oracle_mod):
     rows = plan.autotune(x, y)
     cfgs = [cfg for cfg, _ in rows]
     assert "naive" in cfgs and any(cfg.startswith("k=1,wl=") for cfg in cfgs)
-    assert all("k=2" not in cfg for cfg in cfgs)  # single-step passes only above radius 4
+    assert any(cfg.startswith("k=2,") for cfg in cfgs)  # two fused steps up to radius 6
+    assert all("k=3" not in cfg for cfg in cfgs)
     plan.run(x, y, 3)
     torch.cuda.synchronize()
     assert_bitwise(y.cpu().numpy(), oracle_mod.star_run_f32(f, c, 6, 3), "3D r6 tuned")
-    with pytest.raises(ValueError):  # EINVAL: one step per pass above radius 4
-        st.Plan(shape, 6, c, tune="k=2")
+    with pytest.raises(ValueError):  # EINVAL: at most two fused steps at radius 5, 6
+        st.Plan(shape, 6, c, tune="k=3")
     plan.close()
 
 
@@ -238,6 +254,27 @@ def test_reduce_f64(torch, st, n):
     assert abs(sm - np.sum(xn)) <= 1e-12 * n
     md2, mr2, sm2 = st.reduce_f64(x, None)
     assert (md2, mr2) == (0.0, 0.0) and sm2 == sm
+
+
+def test_reduce_f64_propagates_nan_and_inf(torch, st):
+    """A NaN or an infinite cell is reported, as numpy's max reports it."""
+    n = 300_001
+    base = synth.uniform01_f32(15, n)
+    ref = torch.from_numpy(synth.uniform01_f32(16, n).astype(np.float64)).cuda()
+    for where, val in ((7, np.nan), (n - 1, np.inf), (123_456, -np.inf)):
+        xh = base.copy()
+        xh[where] = val
+        md, mr, sm = st.reduce_f64(torch.from_numpy(xh).cuda(), ref)
+        want = np.max(np.abs(xh.astype(np.float64) - ref.cpu().numpy()))
+        assert (np.isnan(md) and np.isnan(want)) or md == want, (where, val, md, want)
+        assert mr == np.max(np.abs(ref.cpu().numpy()))
+        assert (np.isnan(sm) and np.isnan(np.sum(xh.astype(np.float64)))) or \
+            sm == np.sum(xh.astype(np.float64)) or abs(sm) == np.inf
+    # a NaN in the reference shows in both maxima
+    rh = ref.cpu().numpy().copy()
+    rh[99] = np.nan
+    md, mr, _ = st.reduce_f64(torch.from_numpy(base).cuda(), torch.from_numpy(rh).cuda())
+    assert np.isnan(md) and np.isnan(mr)
 
 
 @pytest.mark.parametrize("shape,radius", [((300, 700), 2), ((30, 40, 300), 1), ((20, 24, 90), 4)])
