@@ -11,6 +11,10 @@ Contents, each with the passage it follows:
   * star_run_f64 / star_run_f32 / star_sample_f64 -- Eq. (1) of Sec. IV.A
     with the clamp-to-border boundary of Sec. III.B / IV.B (C code in
     star_oracle.c).
+  * star_run_padded -- the padded-halo boundary of Sec. IV.B (YASK's larger
+    allocation: a fixed ghost frame read without clamping).
+  * star_run_sym_f32, expand_symmetric -- shared coefficients per axis and
+    distance (Sec. IV.A, Sec. VI.C), in a fixed FP32 order.
   * flop_per_cell, bytes_per_cell -- Table I (Sec. IV.A): 8r+1 / 12r+1 FLOP
     and 8 bytes per cell update under full spatial reuse.
   * gcells_per_s, gflops, gbytes_per_s, roofline_ratio -- Eq. (3) (Sec.
@@ -52,8 +56,12 @@ def lib() -> ctypes.CDLL:
         L.oracle_star_sample_f32.argtypes = [ctypes.c_int, i64p, ctypes.c_int, fp, ctypes.c_int,
                                              fp, ctypes.c_int64, i64p, ctypes.c_int64, fp,
                                              ctypes.c_int]
+        L.oracle_star_run_padded_f64.argtypes = L.oracle_star_run_f64.argtypes
+        L.oracle_star_run_padded_f32.argtypes = L.oracle_star_run_f32.argtypes
+        L.oracle_star_run_sym_f32.argtypes = L.oracle_star_run_f32.argtypes
         for f in (L.oracle_star_run_f64, L.oracle_star_run_f32, L.oracle_star_sample_f64,
-                  L.oracle_star_sample_f32):
+                  L.oracle_star_sample_f32, L.oracle_star_run_padded_f64,
+                  L.oracle_star_run_padded_f32, L.oracle_star_run_sym_f32):
             f.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -162,6 +170,59 @@ def star_sample_f32(f0: np.ndarray, coeffs, radius: int, steps: int, cells,
                                       _ptr(vals, ctypes.c_float), int(threads or max_threads()))
     _check(rc, "star_sample_f32")
     return vals
+
+
+def star_run_padded(f0: np.ndarray, coeffs, radius: int, steps: int, dtype=np.float64,
+                    threads: int = 0) -> np.ndarray:
+    """The padded-halo boundary (Sec. IV.B): f0 is the padded array, the
+    interior surrounded by a fixed ghost frame of `radius` cells on every
+    side; every step applies Eq. (1) to the interior cells, reading
+    neighbours from the array without clamping, and keeps the frame.
+    dtype float64 (the definition) or float32 (the FP32 order of
+    star_run_f32)."""
+    f = np.ascontiguousarray(f0, dtype=dtype)
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    c = np.ascontiguousarray(np.asarray(coeffs), dtype=dtype)
+    if any(n <= 2 * radius for n in f.shape):
+        raise ValueError("star_run_padded: every axis needs an interior (side > 2*radius)")
+    out = np.empty_like(f)
+    dims = _dims_xyz(tuple(n - 2 * radius for n in f.shape))
+    fn = lib().oracle_star_run_padded_f64 if dtype == np.float64 else lib().oracle_star_run_padded_f32
+    rc = fn(f.ndim, _ptr(dims, ctypes.c_int64), int(radius), _ptr(c, ct), int(c.size),
+            _ptr(f, ct), _ptr(out, ct), int(steps), int(threads or max_threads()))
+    _check(rc, "star_run_padded")
+    return out
+
+
+def expand_symmetric(sym, ndim: int, radius: int) -> np.ndarray:
+    """Per-point coefficients of a shared-coefficient star: sym holds c_C,
+    then for i = 1..radius one value per axis (x, y[, z]); both neighbours of
+    an axis and distance take it (W, E <- x; S, N <- y; B, A <- z)."""
+    sym = np.asarray(sym)
+    out = [sym[0]]
+    for i in range(radius):
+        for a in range(ndim):
+            v = sym[1 + i * ndim + a]
+            out += [v, v]
+    return np.array(out, dtype=sym.dtype)
+
+
+def star_run_sym_f32(f0: np.ndarray, sym_coeffs, radius: int, steps: int,
+                     threads: int = 0) -> np.ndarray:
+    """Shared-coefficient star in FP32 (clamp boundary): per cell c_C*f_C,
+    then for i = 1..radius and each axis one fused multiply-add of c_{a,i}
+    with the rounded pair sum f(p - i e_a) + f(p + i e_a).  Its FP64
+    definition is star_run_f64 with expand_symmetric(sym_coeffs)."""
+    f = np.ascontiguousarray(f0, dtype=np.float32)
+    c = np.ascontiguousarray(np.asarray(sym_coeffs), dtype=np.float32)
+    out = np.empty_like(f)
+    dims = _dims_xyz(f.shape)
+    rc = lib().oracle_star_run_sym_f32(f.ndim, _ptr(dims, ctypes.c_int64), int(radius),
+                                       _ptr(c, ctypes.c_float), int(c.size),
+                                       _ptr(f, ctypes.c_float), _ptr(out, ctypes.c_float),
+                                       int(steps), int(threads or max_threads()))
+    _check(rc, "star_run_sym_f32")
+    return out
 
 
 # --- Table I and Eq. (3): work and throughput accounting -------------------

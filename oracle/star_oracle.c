@@ -25,18 +25,24 @@
  *   cell on the border, i.e. each coordinate is clamped to [0, n-1]
  *   independently, at every step, against the current field.
  *
- * Two entry points:
+ * Entry points:
  *   oracle_star_run_f64  -- the definition in double precision: the oracle.
  *   oracle_star_run_f32  -- the same definition evaluated in single
  *     precision with one fixed operation order (the centre product first,
  *     then one fused multiply-add per neighbour in the coefficient order
  *     above).  Used to check that a single-precision implementation that
  *     keeps this order reproduces it bit for bit.
+ *   oracle_star_sample_f64 / _f32 -- the same values at chosen cells, each
+ *     from its own dependence cone.
+ *   oracle_star_run_padded_f64 / _f32 -- the padded-halo boundary of
+ *     Sec. IV.B (fixed ghost frame of width rad, read without clamping).
+ *   oracle_star_run_sym_f32 -- shared coefficients per axis and distance,
+ *     single precision, with the pair sum f_- + f_+ rounded first.
  *
  * Layout: dense, row-major, x fastest: index = x + nx*(y + ny*z).  For 2D,
  * dims[2] is ignored (nz = 1).
  *
- * Build: cc -O2 -fopenmp -ffp-contract=off -shared -fPIC (contraction off so
+ * Build: cc -O3 -fopenmp -ffp-contract=off -shared -fPIC (contraction off so
  * the single-precision form keeps exactly the operations written here).
  */
 #include <math.h>
@@ -393,6 +399,213 @@ int oracle_star_sample_f32(int ndim, const int64_t *dims, int rad,
         free(b);
     }
     return status;
+}
+
+/*
+ * Padded-halo boundary (the YASK arrangement of Sec. IV.B: a larger grid is
+ * allocated and out-of-bound neighbours are read from memory rather than
+ * clamped).  The arrays hold the interior of dims[] cells per axis inside a
+ * frame of `rad` ghost cells on every side, so each axis has dims[a] + 2*rad
+ * cells; index = x + px*(y + py*z) over the padded sizes px, py(, pz).  The
+ * ghost frame holds fixed values (it is never updated): every step applies
+ * Eq. (1) to the interior cells, reading neighbours straight from the padded
+ * array with no clamp, and copies the frame unchanged.  Same arithmetic and
+ * order as the clamp forms above (FP64; FP32 with the centre product, then
+ * one fmaf per neighbour in coefficient order).
+ */
+static int padded_dims(int ndim, const int64_t *dims, int rad, int ncoef, int64_t steps,
+                       int64_t *px, int64_t *py, int64_t *pz)
+{
+    int64_t nx, ny, nz;
+    if (check_args(ndim, dims, rad, ncoef, steps, &nx, &ny, &nz)) return -1;
+    *px = nx + 2 * (int64_t)rad;
+    *py = ny + 2 * (int64_t)rad;
+    *pz = (ndim == 3) ? nz + 2 * (int64_t)rad : 1;
+    return 0;
+}
+
+static void step_padded_f64(int ndim, int64_t px, int64_t py, int64_t pz, int rad,
+                            const double *c, const double *src, double *dst, int nthreads)
+{
+    const int64_t z0 = (ndim == 3) ? rad : 0, z1 = (ndim == 3) ? pz - rad : 1;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
+    for (int64_t z = 0; z < pz; ++z) {
+        for (int64_t y = 0; y < py; ++y) {
+#define F(xx, yy, zz) src[(xx) + px * ((yy) + py * (zz))]
+            for (int64_t x = 0; x < px; ++x) {
+                const int inside = x >= rad && x < px - rad && y >= rad && y < py - rad &&
+                                   z >= z0 && z < z1;
+                if (!inside) {  /* ghost frame: fixed */
+                    dst[x + px * (y + py * z)] = F(x, y, z);
+                    continue;
+                }
+                double acc = c[0] * F(x, y, z);
+                int k = 1;
+                for (int i = 1; i <= rad; ++i) {
+                    acc += c[k++] * F(x - i, y, z);   /* W */
+                    acc += c[k++] * F(x + i, y, z);   /* E */
+                    acc += c[k++] * F(x, y - i, z);   /* S */
+                    acc += c[k++] * F(x, y + i, z);   /* N */
+                    if (ndim == 3) {
+                        acc += c[k++] * F(x, y, z - i); /* B */
+                        acc += c[k++] * F(x, y, z + i); /* A */
+                    }
+                }
+                dst[x + px * (y + py * z)] = acc;
+            }
+#undef F
+        }
+    }
+}
+
+static void step_padded_f32(int ndim, int64_t px, int64_t py, int64_t pz, int rad,
+                            const float *c, const float *src, float *dst, int nthreads)
+{
+    const int64_t z0 = (ndim == 3) ? rad : 0, z1 = (ndim == 3) ? pz - rad : 1;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
+    for (int64_t z = 0; z < pz; ++z) {
+        for (int64_t y = 0; y < py; ++y) {
+#define F(xx, yy, zz) src[(xx) + px * ((yy) + py * (zz))]
+            for (int64_t x = 0; x < px; ++x) {
+                const int inside = x >= rad && x < px - rad && y >= rad && y < py - rad &&
+                                   z >= z0 && z < z1;
+                if (!inside) {
+                    dst[x + px * (y + py * z)] = F(x, y, z);
+                    continue;
+                }
+                float acc = c[0] * F(x, y, z);
+                int k = 1;
+                for (int i = 1; i <= rad; ++i) {
+                    acc = fmaf(c[k], F(x - i, y, z), acc); ++k;
+                    acc = fmaf(c[k], F(x + i, y, z), acc); ++k;
+                    acc = fmaf(c[k], F(x, y - i, z), acc); ++k;
+                    acc = fmaf(c[k], F(x, y + i, z), acc); ++k;
+                    if (ndim == 3) {
+                        acc = fmaf(c[k], F(x, y, z - i), acc); ++k;
+                        acc = fmaf(c[k], F(x, y, z + i), acc); ++k;
+                    }
+                }
+                dst[x + px * (y + py * z)] = acc;
+            }
+#undef F
+        }
+    }
+}
+
+/* `steps` steps of the padded-halo form; f0 and out hold the padded arrays
+ * (they may alias).  Returns 0, -1 on bad arguments, -2 when memory runs out. */
+int oracle_star_run_padded_f64(int ndim, const int64_t *dims, int rad,
+                               const double *coef, int ncoef,
+                               const double *f0, double *out, int64_t steps,
+                               int nthreads)
+{
+    int64_t px, py, pz;
+    if (padded_dims(ndim, dims, rad, ncoef, steps, &px, &py, &pz)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t n = (size_t)px * (size_t)py * (size_t)pz;
+    double *a = (double *)malloc(n * sizeof(double));
+    double *b = (double *)malloc(n * sizeof(double));
+    if (!a || !b) { free(a); free(b); return -2; }
+    memcpy(a, f0, n * sizeof(double));
+    for (int64_t t = 0; t < steps; ++t) {
+        step_padded_f64(ndim, px, py, pz, rad, coef, a, b, nthreads);
+        double *tmp = a; a = b; b = tmp;
+    }
+    memcpy(out, a, n * sizeof(double));
+    free(a);
+    free(b);
+    return 0;
+}
+
+int oracle_star_run_padded_f32(int ndim, const int64_t *dims, int rad,
+                               const float *coef, int ncoef,
+                               const float *f0, float *out, int64_t steps,
+                               int nthreads)
+{
+    int64_t px, py, pz;
+    if (padded_dims(ndim, dims, rad, ncoef, steps, &px, &py, &pz)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t n = (size_t)px * (size_t)py * (size_t)pz;
+    float *a = (float *)malloc(n * sizeof(float));
+    float *b = (float *)malloc(n * sizeof(float));
+    if (!a || !b) { free(a); free(b); return -2; }
+    memcpy(a, f0, n * sizeof(float));
+    for (int64_t t = 0; t < steps; ++t) {
+        step_padded_f32(ndim, px, py, pz, rad, coef, a, b, nthreads);
+        float *tmp = a; a = b; b = tmp;
+    }
+    memcpy(out, a, n * sizeof(float));
+    free(a);
+    free(b);
+    return 0;
+}
+
+/*
+ * Shared-coefficient (symmetric) star, single precision, clamp boundary.
+ * Sec. IV.A notes that the paper's instance shares one coefficient per
+ * direction while its design targets the case where all coefficients
+ * differ; the comparison codes of Sec. VI.C use shared coefficients.  Here
+ * the two neighbours at distance i along one axis share one coefficient:
+ * coef holds 1 + ndim*rad values, c_C then for i = 1..rad the axes x, y(, z).
+ * Each cell is evaluated in this fixed order, one rounding per operation:
+ *   acc = c_C * f_C
+ *   for i = 1..rad, for each axis a in x, y(, z):
+ *       s   = f(p - i e_a) + f(p + i e_a)          (the pair's sum)
+ *       acc = fmaf(c_{a,i}, s, acc)
+ * In exact arithmetic this is Eq. (1) with c_W,i = c_E,i = c_x,i and so on;
+ * the FP64 definition is therefore oracle_star_run_f64 with the
+ * coefficients expanded per point.
+ */
+static void step_sym_f32(int ndim, int64_t nx, int64_t ny, int64_t nz, int rad,
+                         const float *c, const float *src, float *dst, int nthreads)
+{
+#pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t y = 0; y < ny; ++y) {
+            for (int64_t x = 0; x < nx; ++x) {
+#define F(xx, yy, zz) src[(xx) + nx * ((yy) + ny * (zz))]
+                float acc = c[0] * F(x, y, z);
+                int k = 1;
+                for (int i = 1; i <= rad; ++i) {
+                    float s = F(clamp_index(x - i, nx), y, z) + F(clamp_index(x + i, nx), y, z);
+                    acc = fmaf(c[k], s, acc); ++k;
+                    s = F(x, clamp_index(y - i, ny), z) + F(x, clamp_index(y + i, ny), z);
+                    acc = fmaf(c[k], s, acc); ++k;
+                    if (ndim == 3) {
+                        s = F(x, y, clamp_index(z - i, nz)) + F(x, y, clamp_index(z + i, nz));
+                        acc = fmaf(c[k], s, acc); ++k;
+                    }
+                }
+                dst[x + nx * (y + ny * z)] = acc;
+#undef F
+            }
+        }
+    }
+}
+
+int oracle_star_run_sym_f32(int ndim, const int64_t *dims, int rad,
+                            const float *coef, int ncoef,
+                            const float *f0, float *out, int64_t steps,
+                            int nthreads)
+{
+    int64_t nx, ny, nz;
+    /* check_args counts per-point coefficients: pass that count */
+    if (ncoef != 1 + ndim * rad) return -1;
+    if (check_args(ndim, dims, rad, 1 + 2 * ndim * rad, steps, &nx, &ny, &nz)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    size_t n = (size_t)nx * (size_t)ny * (size_t)nz;
+    float *a = (float *)malloc(n * sizeof(float));
+    float *b = (float *)malloc(n * sizeof(float));
+    if (!a || !b) { free(a); free(b); return -2; }
+    memcpy(a, f0, n * sizeof(float));
+    for (int64_t t = 0; t < steps; ++t) {
+        step_sym_f32(ndim, nx, ny, nz, rad, coef, a, b, nthreads);
+        float *tmp = a; a = b; b = tmp;
+    }
+    memcpy(out, a, n * sizeof(float));
+    free(a);
+    free(b);
+    return 0;
 }
 
 int oracle_max_threads(void)
