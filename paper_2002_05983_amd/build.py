@@ -50,14 +50,32 @@ def _obj_name(src: str, defs: dict) -> str:
     return f"{stem}{suffix}.o"
 
 
+def _includes(path: str, seen: set) -> set:
+    """The local headers `path` includes, directly or through other headers."""
+    try:
+        with open(path) as fh:
+            text = fh.read()
+    except OSError:
+        return seen
+    for line in text.splitlines():
+        line = line.strip()
+        if line.startswith("#include") and '"' in line:
+            name = line.split('"')[1]
+            for d in (CSRC, INCLUDE):
+                h = os.path.join(d, name)
+                if os.path.exists(h) and h not in seen:
+                    seen.add(h)
+                    _includes(h, seen)
+                    break
+    return seen
+
+
 def _stale(obj: str, src: str) -> bool:
-    """An object is stale when older than its source or any header."""
+    """An object is stale when older than its source or a header it includes."""
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
-    headers += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
-    return any(os.path.getmtime(f) > t for f in [src] + headers)
+    return any(os.path.getmtime(f) > t for f in [src, *_includes(src, set())])
 
 
 def build(verbose: bool = False, asm_dir: str | None = None, jobs: int | None = None,
