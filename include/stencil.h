@@ -138,6 +138,29 @@ STENCIL_API int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *d
  */
 STENCIL_API int stencil_run(stencil_plan_t plan, const float *in, float *out, int64_t steps, void *stream);
 
+/* Largest grid, in cells, that stencil_run_noalloc accepts: 2^24 cells (a
+ * 64 MiB FP32 partner grid, held on every device the call runs on until the
+ * process ends). */
+#define STENCIL_NOALLOC_MAX_CELLS 16777216
+
+/*
+ * stencil_run for callers that cannot allocate device memory while they run
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, pass schedule and result, bit for bit, but
+ * the ping-pong partner grid is a fixed device array of the library instead
+ * of the plan's scratch, so the call performs no hipMalloc, hipFree or other
+ * allocation.
+ *   plan     an FP32-storage plan (EUNSUPPORTED otherwise) of at most
+ *            STENCIL_NOALLOC_MAX_CELLS cells (EUNSUPPORTED otherwise).
+ *   in, out  as for stencil_run; they must not overlap the static array.
+ * The array's device address is looked up on the first call on each
+ * device.  All calls on one device share that device's array: calls that
+ * overlap in time on one device race, so order them (one stream, or
+ * events).  Errors: EINVAL, EUNSUPPORTED, EDEVICE.
+ */
+STENCIL_API int stencil_run_noalloc(stencil_plan_t plan, const float *in, float *out, int64_t steps,
+                                    void *stream);
+
 /*
  * Runs n independent grids, grid g with plans[g], ins[g], outs[g] and
  * steps[g] (host arrays of length n, device grid pointers), with the same

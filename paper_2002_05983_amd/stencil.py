@@ -31,6 +31,7 @@ SIGNATURES = {
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_char_p]),
     "stencil_run": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "stencil_run_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "stencil_run_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), _i64p, _vp]),
     "stencil_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
@@ -139,6 +140,16 @@ class Plan:
         _check_grid(out, self.ncells, "out")
         _check(load().stencil_run(self._h, inp.data_ptr(), out.data_ptr(), int(steps),
                                   _stream_ptr(stream)))
+        return out
+
+    def run_noalloc(self, inp, out, steps: int, stream=None):
+        """run() without device allocation (stencil_run_noalloc): the
+        partner grid is the library's static array, shared by every call on
+        the device."""
+        _check_grid(inp, self.ncells, "inp")
+        _check_grid(out, self.ncells, "out")
+        _check(load().stencil_run_noalloc(self._h, inp.data_ptr(), out.data_ptr(), int(steps),
+                                          _stream_ptr(stream)))
         return out
 
     def query(self) -> dict:
