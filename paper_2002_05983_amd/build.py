@@ -27,6 +27,7 @@ ARCH = "gfx950"
 HOST_UNITS = ["api.cpp", "plan.cpp", "tune.cpp", "lowp.cpp", "batch.cpp", "model.cpp"]
 DEVICE_UNITS = [("naive.hip", {}), ("reduce.hip", {}), ("noalloc.hip", {})] + [("star2d.hip", {"STAR_R": r}) for r in range(1, 9)]
 DEVICE_UNITS += [("star3d.hip", {"STAR_R": r}) for r in range(1, 9)]
+DEVICE_UNITS += [("star3d_rows.hip", {"STAR_R": r}) for r in range(1, 9)]
 DEVICE_UNITS += [("lowp3d.hip", {"STAR_R": r}) for r in (1, 2, 3, 4)] + [("lowp_util.hip", {})]
 DEVICE_UNITS += [(f"batch{d}d.hip", {"STAR_R": r}) for d in (2, 3) for r in (1, 2, 3, 4)]
 

@@ -52,6 +52,8 @@ struct Star3DArgs {
     int lz;       // output planes per z-segment
     bool pair;    // two planes per barrier (k = 1, vec = 4)
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
+    int rows = 0; // LDS-free single-step layout: grid rows per wavefront (1, 2), 0 = xy tiles
+    bool nbp = false;  // rows layout: neighbour rows loaded one plane ahead
     Coefs cf;
 };
 // Largest K built per radius: the tile keeps >= 8 output rows of 16 for
@@ -68,5 +70,16 @@ hipError_t launch_star3d_r5(const Star3DArgs &a, hipStream_t stream);
 hipError_t launch_star3d_r6(const Star3DArgs &a, hipStream_t stream);
 hipError_t launch_star3d_r7(const Star3DArgs &a, hipStream_t stream);
 hipError_t launch_star3d_r8(const Star3DArgs &a, hipStream_t stream);
+
+// LDS-free 3D single-step pass: whole 256-column rows per wavefront, z
+// streamed, y-neighbour rows loaded from the caches (star3d_rows.hpp).
+hipError_t launch_star3d_rows_r1(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r2(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r3(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r4(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r5(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r6(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r7(const Star3DArgs &a, hipStream_t stream);
+hipError_t launch_star3d_rows_r8(const Star3DArgs &a, hipStream_t stream);
 
 }  // namespace star

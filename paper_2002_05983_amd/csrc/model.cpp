@@ -115,6 +115,28 @@ Pass model_3d(const stencil_plan_s *p, int K) {
     return s;
 }
 
+// LDS-free single-step layout: no redundant cells, every wavefront
+// independent; bounded by HBM (one read and one write per cell, plus the
+// 2R wind-up planes of each segment) or by VALU issue (4 cells per lane:
+// one FMA per point, 2R lane shifts, a per-row overhead).
+constexpr double kRow3R = 12.0;
+
+Pass model_3r(const stencil_plan_s *p) {
+    const int R = p->radius;
+    const double nx = (double)p->nx, ny = (double)p->ny, nz = (double)p->nz;
+    const double lz = std::min<double>(p->s3_lz, nz);
+    const double nstrips = std::ceil(nx / 256.0), nyb = std::ceil(ny / p->s3_rpl);
+    const double nseg = std::ceil(nz / lz);
+    const double waves = nstrips * nyb * nseg;
+    const double per_row = 4.0 * (6.0 * R + 1.0) + 2.0 * R + kRow3R;
+    Pass s;
+    s.t_valu = waves * lz * p->s3_rpl * per_row * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
+    s.t_plane = 0.0;
+    const double cells = nx * ny * nz;
+    s.t_hbm = (cells * 4.0 * (lz + 2.0 * R) / lz + cells * 4.0) / kHbmEff3D;
+    return s;
+}
+
 }  // namespace
 
 extern "C" int stencil_plan_model(stencil_plan_t plan, const char *config, double out[4]) {
@@ -127,7 +149,9 @@ extern "C" int stencil_plan_model(stencil_plan_t plan, const char *config, doubl
     }
     if (trial.variant == STAR_NAIVE || trial.storage != STENCIL_F32)
         return star_set_error(STENCIL_EUNSUPPORTED, "the model covers the FP32 streaming kernels");
-    const Pass s = trial.ndim == 2 ? model_2d(&trial, trial.K) : model_3d(&trial, trial.K);
+    const Pass s = trial.ndim == 2 ? model_2d(&trial, trial.K)
+                   : trial.s3_rpl > 0 ? model_3r(&trial)
+                                      : model_3d(&trial, trial.K);
     const double t =
         std::max({s.t_hbm, s.t_valu, s.t_plane}) + (trial.ndim == 2 ? kLaunch2D : kLaunch3D);
     out[0] = (double)trial.ncells * trial.K / t / 1e9;

@@ -56,6 +56,19 @@ int default_lz(const stencil_plan_s *p) {
     return (int)std::max<int64_t>(lz, 1);
 }
 
+// z-segment length of the LDS-free single-step layout: about 4096
+// wavefronts (16 per CU), segments of at least 8R planes
+// (the 2R wind-up planes are loads only).
+int default_lz_rows(const stencil_plan_s *p) {
+    const int64_t strips = (p->nx + 255) / 256;
+    const int64_t blocks = strips * ((p->ny + p->s3_rpl - 1) / p->s3_rpl);
+    const int64_t nseg = std::max<int64_t>(1, (4096 + blocks - 1) / blocks);
+    int64_t lz = (p->nz + nseg - 1) / nseg;
+    lz = std::max<int64_t>(lz, 8 * p->radius);
+    lz = std::min<int64_t>(lz, p->nz);
+    return (int)std::max<int64_t>(lz, 1);
+}
+
 bool parse_int(const char *s, int *out) {
     char *end = nullptr;
     long v = strtol(s, &end, 10);
@@ -103,12 +116,18 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->s3_lanes = 32;
         p->s3_lz = 0;
         p->s3_pair = 0;
-        // Above radius 4 the streaming kernel's z-queue of 2R+1 planes no
+        p->s3_rpl = 0;
+        p->s3_nbp = 0;
+        // Above radius 5 the xy-tile kernel's z-queue of 2R+1 planes no
         // longer fits a 1024-thread workgroup's 128 VGPRs (it spills) and 2R
-        // of its 32 tile rows are halo: measured on 512^3 it is 3.5x and
-        // 1.7x the single-step kernel at R = 5, 6, and about even at 7, 8,
-        // where the single-step kernel is the default
-        if (R >= 7) p->variant = STAR_NAIVE;
+        // of its 32 tile rows are halo; the LDS-free row layout keeps every
+        // cell an output cell and runs without spills: measured on 512^3 it
+        // is 1.35x, 3.3x and 5.3x the best other single-step form at
+        // R = 6, 7, 8 (the xy-tile kernel stays ahead at R <= 5)
+        if (R >= 6 && p->storage == STENCIL_F32) {
+            p->s3_rpl = 1;
+            p->s3_nbp = p->nx % 4 == 0 ? 1 : 0;
+        }
     }
     p->ly = (p->ndim == 2) ? 0 : p->ly;
     if (tune && *tune) {
@@ -123,17 +142,24 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             if (item == "naive" && p->storage == STENCIL_F32) {
                 p->variant = STAR_NAIVE;
                 p->K = 1;
+                p->s3_rpl = p->s3_nbp = 0;
                 continue;
             }
             size_t eq = item.find('=');
             if (eq == std::string::npos)
                 return star_set_error(STENCIL_EINVAL, ("bad tune item '" + item + "'").c_str());
             std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+            if (key == "nbp" && p->ndim == 3 && (val == "0" || val == "1")) {
+                p->s3_nbp = val == "1";
+                p->variant = STAR_S3D;
+                continue;
+            }
             int v = 0;
             if (!parse_int(val.c_str(), &v) || v < 1)
                 return star_set_error(STENCIL_EINVAL, ("bad tune value '" + item + "'").c_str());
             if (key == "k") {
                 p->K = v;
+                if (v != 1) p->s3_rpl = p->s3_nbp = 0;  // the row layout is single-step
             } else if (key == "ly" && p->ndim == 2) {
                 p->ly = v;
             } else if (key == "lz" && p->ndim == 3) {
@@ -141,16 +167,23 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 p->variant = STAR_S3D;
             } else if (key == "nw" && p->ndim == 3) {
                 p->s3_rows = v;
+                p->s3_rpl = p->s3_nbp = 0;  // an xy-tile key selects the xy-tile kernel
                 p->variant = STAR_S3D;
             } else if (key == "vec" && p->ndim == 3) {
                 p->vec = v;
+                p->s3_rpl = p->s3_nbp = 0;
                 p->variant = STAR_S3D;
             } else if (key == "wl" && p->ndim == 3) {
                 p->s3_lanes = v;
+                p->s3_rpl = p->s3_nbp = 0;
+                p->variant = STAR_S3D;
+            } else if (key == "rows" && p->ndim == 3) {
+                p->s3_rpl = v;
                 p->variant = STAR_S3D;
             } else if (key == "pair" && p->ndim == 3) {
                 if (v != 1) return star_set_error(STENCIL_EINVAL, "pair takes the value 1");
                 p->s3_pair = 1;
+                p->s3_rpl = p->s3_nbp = 0;
                 p->variant = STAR_S3D;
 
             } else {
@@ -184,6 +217,23 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         }
         if (p->K < 1 || p->K > max_k3d(R))
             return star_set_error(STENCIL_EINVAL, "3D k must be 1..4 for R = 1, 1..3 for R = 2, 3, 1..2 for R = 4..6, 1 above");
+        if (p->s3_rpl > 0 || p->s3_nbp) {
+            // LDS-free single-step layout: whole 256-column rows per wavefront
+            if (p->s3_rpl == 0) p->s3_rpl = 1;
+            if (p->K != 1 || p->storage != STENCIL_F32 || p->s3_pair)
+                return star_set_error(STENCIL_EINVAL, "rows= is a single-step FP32 layout (k=1, no pair)");
+            if (p->s3_rpl > 2 || (p->s3_rpl == 2 && R > 4))
+                return star_set_error(STENCIL_EINVAL, "rows must be 1, or 2 for R <= 4");
+            if ((p->s3_rpl == 2 || p->s3_nbp) && p->nx % 4 != 0)
+                return star_set_error(STENCIL_EINVAL, "rows=2 and nbp=1 need rows of 16 bytes (nx % 4 == 0)");
+            if (p->s3_lz == 0) p->s3_lz = default_lz_rows(p);
+            if (p->s3_lz < 1) return star_set_error(STENCIL_EINVAL, "lz must be >= 1");
+            p->vec = 4;
+            p->tile[0] = 256;
+            p->tile[1] = p->s3_rpl;
+            p->tile[2] = p->s3_lz;
+            return STENCIL_OK;
+        }
         if (p->s3_lanes != 64 && p->s3_lanes != 32)
             return star_set_error(STENCIL_EINVAL, "3D wl must be 64 or 32");
         const int rows = p->s3_rows * (64 / p->s3_lanes);
@@ -284,6 +334,23 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
             a.aligned = (p->nx % 4 == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
             if (a.vec == 8 && !a.aligned) a.vec = 4;
             a.cf = p->cf;
+            if (p->s3_rpl > 0 && k == 1) {
+                // LDS-free layout; grids not 16-byte aligned take its
+                // one-row form without prefetched neighbour rows
+                a.rows = a.aligned ? p->s3_rpl : 1;
+                a.nbp = a.aligned && p->s3_nbp;
+                switch (p->radius) {
+                    case 1: return launch_star3d_rows_r1(a, stream);
+                    case 2: return launch_star3d_rows_r2(a, stream);
+                    case 3: return launch_star3d_rows_r3(a, stream);
+                    case 4: return launch_star3d_rows_r4(a, stream);
+                    case 5: return launch_star3d_rows_r5(a, stream);
+                    case 6: return launch_star3d_rows_r6(a, stream);
+                    case 7: return launch_star3d_rows_r7(a, stream);
+                    case 8: return launch_star3d_rows_r8(a, stream);
+                }
+                return hipErrorInvalidValue;
+            }
             switch (p->radius) {
                 case 1: return launch_star3d_r1(a, stream);
                 case 2: return launch_star3d_r2(a, stream);
@@ -304,7 +371,10 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
 std::string plan_describe(const stencil_plan_s *p) {
     char buf[256];
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
-    if (p->variant == STAR_S3D)
+    if (p->variant == STAR_S3D && p->s3_rpl > 0)
+        snprintf(buf, sizeof buf, "variant=s3d ndim=3 R=%d K=1 layout=rows rows=%d nbp=%d lz=%d by=%s",
+                 p->radius, p->s3_rpl, p->s3_nbp, p->s3_lz, p->tuned_by.c_str());
+    else if (p->variant == STAR_S3D)
         snprintf(buf, sizeof buf,
                  "variant=%s ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d%s%s by=%s",
                  p->storage == STENCIL_F32 ? "s3d"

@@ -42,6 +42,8 @@ struct stencil_plan_s {
     int s3_rows = 16;   // tile rows (halo included) per workgroup
     int s3_lz = 64;     // output planes per z-segment
     int s3_pair = 0;    // 1: two planes per barrier (single-step passes)
+    int s3_rpl = 0;     // > 0: LDS-free single-step layout, grid rows per wavefront
+    int s3_nbp = 0;     // rows layout: neighbour rows loaded one plane ahead
     std::string tuned_by = "default";
 };
 

@@ -1,0 +1,83 @@
+// star3d_rows.hip -- single-grid launch of the LDS-free 3D single-step pass
+// (method in star3d_rows.hpp).
+//
+// Compiled once per radius with -DSTAR_R=<1..8>.
+#include "star3d_rows.hpp"
+
+#ifndef STAR_R
+#error "compile with -DSTAR_R=<radius>"
+#endif
+
+namespace star {
+
+namespace {
+
+using s3r::prefetch_rows3;
+using s3r::STRIP;
+using s3r::star3d_rows_body;
+
+// Four wavefronts per workgroup, each independent.  Wavefront w takes strip
+// w % nstrips of row block (w / nstrips) % nyb and z-segment w / (nstrips *
+// nyb): consecutive wavefronts (one workgroup, one CU; and, through the
+// XCD-aware block order, one L2) hold neighbouring strips and row blocks
+// at the same planes, so the y-neighbour rows they load from each other
+// are cache hits.  WPE: waves per SIMD the register budget is sized for.
+template <int R, int RPL, bool NBP, bool AL, int WPE>
+__global__ __launch_bounds__(256, WPE) void star3d_rows(const float *__restrict__ src,
+                                                        float *__restrict__ dst, int nx, int ny,
+                                                        int nz, int nstrips, int nyb, int lz,
+                                                        int nwaves, Coefs cf) {
+    const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 +
+                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int strip = wave % nstrips;
+    const int yb = (wave / nstrips) % nyb;
+    const int zseg = wave / (nstrips * nyb);
+    constexpr int D = prefetch_rows3<R, RPL>();
+    if (AL && (strip + 1) * STRIP > nx)
+        star3d_rows_body<R, RPL, D, NBP, AL, true>(src, dst, nx, ny, nz, strip, yb * RPL,
+                                                   zseg * lz, lz, cf);
+    else
+        star3d_rows_body<R, RPL, D, NBP, AL, false>(src, dst, nx, ny, nz, strip, yb * RPL,
+                                                    zseg * lz, lz, cf);
+}
+
+template <int RPL, bool NBP, bool AL>
+hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
+    const int nstrips = (a.nx + STRIP - 1) / STRIP;
+    const int nyb = (a.ny + RPL - 1) / RPL;
+    const int nseg = (a.nz + a.lz - 1) / a.lz;
+    const int64_t nwaves = (int64_t)nstrips * nyb * nseg;
+    if (nwaves > ((int64_t)1 << 30)) return hipErrorInvalidValue;
+    if ((int64_t)a.nx * a.ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    // 4 waves per SIMD (128 VGPRs) where the ring and neighbour rows fit,
+    // else 2 (256 VGPRs): two rows per wavefront, radius >= 5, and the
+    // heavier radius-4 forms
+    constexpr int R = STAR_R;
+    constexpr int WPE = (RPL == 1 && (R <= 3 || (R == 4 && AL && !NBP))) ? 4 : 2;
+    const unsigned blocks = (unsigned)((nwaves + 3) / 4);
+    hipLaunchKernelGGL((star3d_rows<STAR_R, RPL, NBP, AL, WPE>), dim3(blocks), dim3(256), 0, stream,
+                       a.src, a.dst, a.nx, a.ny, a.nz, nstrips, nyb, a.lz, (int)nwaves, a.cf);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define STAR_CAT2(a, b) a##b
+#define STAR_CAT(a, b) STAR_CAT2(a, b)
+
+hipError_t STAR_CAT(launch_star3d_rows_r, STAR_R)(const Star3DArgs &a, hipStream_t stream) {
+    if (a.lz < 1 || a.nx < 1 || a.ny < 1 || a.nz < 1 || a.K != 1) return hipErrorInvalidValue;
+    if (!a.aligned) {
+        if (a.rows != 1 || a.nbp) return hipErrorInvalidValue;  // built for one row, no prefetch
+        return launch_rows<1, false, false>(a, stream);
+    }
+    if (a.rows == 1) return a.nbp ? launch_rows<1, true, true>(a, stream) : launch_rows<1, false, true>(a, stream);
+    if constexpr (STAR_R <= 4) {
+        if (a.rows == 2)
+            return a.nbp ? launch_rows<2, true, true>(a, stream) : launch_rows<2, false, true>(a, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace star

@@ -63,6 +63,20 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                 out.push_back(buf);
             }
     } else {
+        if (p->storage == STENCIL_F32) {
+            // LDS-free single-step layout: rows per wavefront, neighbour-row
+            // prefetch, segment length
+            for (int rows : {1, 2})
+                for (int nbp : {0, 1}) {
+                    if (rows == 2 && R > 4) continue;
+                    if ((rows == 2 || nbp) && p->nx % 4 != 0) continue;
+                    for (int lz : {32, 64, 128, 256}) {
+                        if (lz > p->nz && lz != 32) continue;
+                        snprintf(buf, sizeof buf, "k=1,rows=%d,nbp=%d,lz=%d", rows, nbp, lz);
+                        out.push_back(buf);
+                    }
+                }
+        }
         const int kmax = p->storage == STENCIL_F32 ? max_k3d(R) : 1;
         for (int K = 1; K <= kmax; ++K)
             for (int wl : {64, 32})

@@ -163,6 +163,15 @@ def test_batch_entry_points_reject_null(lib):
     (3, [64, 64, 64], 4, b"k=1,nw=4,wl=64", False),     # 4 rows < 2*K*R+1
     (3, [64, 64, 64], 4, b"k=1,nw=5,wl=32", True),
     (3, [64, 64, 64], 1, b"wl=16", False),
+    (3, [64, 64, 64], 4, b"k=1,rows=2,nbp=1,lz=32", True),
+    (3, [64, 64, 64], 5, b"k=1,rows=1,nbp=0", True),
+    (3, [64, 64, 64], 5, b"k=1,rows=2", False),          # two rows per wavefront up to R = 4
+    (3, [63, 64, 64], 2, b"k=1,rows=2", False),          # ... on 16-byte rows
+    (3, [63, 64, 64], 2, b"k=1,rows=1,nbp=1", False),
+    (3, [63, 64, 64], 2, b"k=1,rows=1,nbp=0", True),
+    (3, [64, 64, 64], 2, b"k=2,rows=1", False),          # single-step layout
+    (3, [64, 64, 64], 2, b"k=1,rows=3", False),
+    (3, [64, 64, 64], 2, b"k=1,nbp=2", False),
     (3, [64, 64, 64], 1, b"k=2,bogus=3", False),
     (3, [64, 64, 64], 1, b"k=x", False),
 ])

@@ -146,6 +146,35 @@ def test_s3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
             assert_bitwise(got, oracle_mod.star_run_f32(f, c, radius, 3), f"s3d vec8 {shape} r{radius}")
 
 
+# (nz, ny, nx): one strip, several strips, ragged strips, nx not a
+# multiple of 4, sides below the radius, row counts not a multiple of 2.
+S3R_SHAPES = [(1, 1, 1), (3, 2, 5), (9, 17, 33), (20, 37, 300), (7, 33, 600), (13, 40, 513),
+              (6, 3, 257), (11, 9, 512), (5, 6, 260), (4, 7, 768)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("shape", S3R_SHAPES)
+def test_s3d_rows_layout_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    """The LDS-free single-step layout: one and two rows per wavefront,
+    with and without prefetched neighbour rows, segments shorter and longer
+    than the grid, several passes."""
+    c = synth.coefficients(720 + radius, 3, radius)
+    f = synth.grid_uniform(820 + radius, shape)
+    want = oracle_mod.star_run_f32(f, c, radius, 3)
+    aligned = shape[2] % 4 == 0
+    for rows in (1, 2):
+        for nbp in (0, 1):
+            if rows == 2 and radius > 4:
+                continue
+            if (rows == 2 or nbp) and not aligned:
+                continue
+            for lz in (1, 4, 64):
+                tune = f"k=1,rows={rows},nbp={nbp},lz={lz}"
+                got, desc = gpu_run(torch, st, f, radius, c, 3, tune=tune)
+                assert "layout=rows" in desc, desc
+                assert_bitwise(got, want, f"s3d rows {shape} r{radius} [{desc}]")
+
+
 @pytest.mark.parametrize("radius", [1, 2, 3, 4])
 def test_s3d_default_config_vs_fp64(torch, st, oracle_mod, radius):
     shape = (40, 45, 130)
@@ -416,6 +445,8 @@ def test_model_predictions_and_errors(torch, st):
     p3 = st.Plan((64, 64, 256), 4, synth.coefficients(4, 3, 4))
     m3 = p3.model("k=1,wl=32,lz=64")
     assert m3["GCell/s"] > 0 and m3["plane_us"] > 0
+    m3r = p3.model("k=1,rows=1,lz=64")  # the LDS-free layout has no plane latency term
+    assert m3r["GCell/s"] > 0 and m3r["hbm_us"] > 0 and m3r["plane_us"] == 0
     pn = st.Plan((64, 64), 1, synth.coefficients(5, 2, 1), tune="naive")
     with pytest.raises(st.StencilError):
         pn.model()
