@@ -309,6 +309,55 @@ def bench_3d_high(stencil, synth, torch, dev, side=512, time_steps=50, reps=2, t
             "per_radius": rows}
 
 
+def bench_forms(stencil, synth, torch, dev, side2=SIDE, side3=512, time_steps2=200,
+                time_steps3=50, reps=2):
+    """Shared coefficients and the padded-halo boundary next to the per-point
+    clamp form, each pair in the same kernel configuration: 2D r=1..4 on
+    side2^2 at K = min(4, 16/R) (the shared form is built up to K = 4) and
+    3D r=1..4 on side3^3 in the single-step row layout (the one layout the
+    3D shared form runs).  The padded grids add a frame of R cells per side
+    (cells counted: the interior)."""
+    import numpy as np
+
+    def timed(plan, x, y, steps):
+        plan.run(x, y, steps)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        a.record(torch.cuda.current_stream(dev))
+        for _ in range(reps):
+            plan.run(x, y, steps)
+        b.record(torch.cuda.current_stream(dev))
+        torch.cuda.synchronize(dev)
+        return a.elapsed_time(b) / reps
+
+    rows = []
+    for ndim, side, steps in ((2, side2, time_steps2), (3, side3, time_steps3)):
+        shape = (side,) * ndim
+        cells = side ** ndim
+        for r in RADII:
+            tune = f"k={min(4, 16 // r)},ly=256" if ndim == 2 else "k=1,rows=1,nbp=1,lz=128"
+            c = synth.coefficients(4000 + 10 * ndim + r, ndim, r)
+            w = 1.0 + synth.uniform01_f64(4100 + 10 * ndim + r, 1 + ndim * r)
+            sym = (w / (w[0] + 2.0 * w[1:].sum())).astype(np.float32)
+            row = {"ndim": ndim, "radius": r, "config": tune}
+            for name, kw, coeffs in (("per_point", {}, c), ("shared", {"symmetric": True}, sym),
+                                     ("padded", {"boundary": "padded"}, c)):
+                p = stencil.Plan(shape, r, coeffs, tune=tune, **kw)
+                x = torch.from_numpy(synth.grid_uniform(ndim, p.array_shape)).to(dev)
+                y = torch.empty_like(x)
+                ms = timed(p, x, y, steps)
+                row[f"{name}_GCell/s"] = round(cells * steps / (ms / 1e3) / 1e9, 1)
+                p.close()
+                del x, y
+            row["shared_over_per_point"] = round(row["shared_GCell/s"] / row["per_point_GCell/s"], 3)
+            row["padded_over_clamp"] = round(row["padded_GCell/s"] / row["per_point_GCell/s"], 3)
+            rows.append(row)
+        torch.cuda.empty_cache()
+    return {"workload": f"per-point clamp vs shared coefficients vs padded halo, same configuration: "
+                        f"2D r=1..4 {side2}^2 ({time_steps2} steps), 3D r=1..4 {side3}^3 "
+                        f"({time_steps3} steps, row layout), FP32 U[0,1)", "rows": rows}
+
+
 def read_fp64_reference(name):
     """Stored FP64 oracle values of a full-size workload at its full step
     count (tests/golden/fp64_<name>.txt): header fields, sampled cells
@@ -516,6 +565,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-high", action="store_true", help="skip the radius 5..8 legs")
     ap.add_argument("--no-single", action="store_true", help="skip the single-step (K=1) leg")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the shared-coefficient / padded-halo leg")
     ap.add_argument("--side", type=int, default=SIDE, help=argparse.SUPPRESS)
     ap.add_argument("--time-steps", type=int, default=TIME_STEPS, help=argparse.SUPPRESS)
     ap.add_argument("--config", action="append", default=[], metavar="R:TUNE", help=argparse.SUPPRESS)
@@ -684,6 +735,9 @@ def main():
         progress(f"2D r=5..8: {extra['2d_high_radius']['GCell/s']} GCell/s")
         extra["3d_high_radius"] = bench_3d_high(stencil, synth, torch, dev, tune=not args.no_tune)
         progress(f"3D r=5..8: {extra['3d_high_radius']['GCell/s']} GCell/s")
+    if not args.no_forms:
+        extra["forms"] = bench_forms(stencil, synth, torch, dev, side2=side)
+        progress("forms done")
     if not args.no_3d:
         extra["3d"] = bench_3d(stencil, synth, torch, dev, tune=not args.no_tune)
         progress(f"3D: {extra['3d']['GCell/s']} GCell/s")

@@ -58,7 +58,9 @@ enum stencil_status {
 };
 
 enum stencil_boundary {
-    STENCIL_BOUNDARY_CLAMP = 0 /* border cell replaces out-of-grid cells (Sec. III.B) */
+    STENCIL_BOUNDARY_CLAMP = 0,  /* border cell replaces out-of-grid cells (Sec. III.B)     */
+    STENCIL_BOUNDARY_PADDED = 1  /* fixed ghost frame of `radius` cells read from memory
+                                    (the larger allocation of Sec. IV.B)                    */
 };
 
 enum stencil_storage {
@@ -77,13 +79,22 @@ enum stencil_storage {
  *            4 bytes must fit in int64.
  *   radius   1..8.  The paper's diffusion stencils have radius 1..4; the
  *            higher radii follow its scaling discussion (Sec. VI.A).  In 3D
- *            above radius 4 only single-step passes are built (the
- *            streaming kernel at k = 1, or the one-thread-per-cell kernel,
- *            the default at radius 7 and 8); low-precision storage is built
- *            for radius 1..4 (EUNSUPPORTED above).
+ *            at most 4/3/3/2/2/2/1/1 steps are fused per pass for radius
+ *            1..8 (the row layout of single-step passes is the default at
+ *            radius 6..8); low-precision storage is built for radius 1..4
+ *            (EUNSUPPORTED above).
  *   coeffs   host array of ncoeffs FP32 values in the order given above.
  *   ncoeffs  must equal 1 + 2*ndim*radius.
- *   boundary STENCIL_BOUNDARY_CLAMP (the only boundary of the paper).
+ *   boundary STENCIL_BOUNDARY_CLAMP: every out-of-grid neighbour takes the
+ *            nearest border cell (Sec. III.B).
+ *            STENCIL_BOUNDARY_PADDED: the padded-halo arrangement of
+ *            Sec. IV.B.  dims are the interior extents; every array the
+ *            plan runs on holds (dims[a] + 2*radius) cells per axis, the
+ *            interior at offset radius on every axis, inside a ghost frame
+ *            of `radius` cells that is never updated: each step applies
+ *            Eq. (1) to the interior cells with the neighbours read from the
+ *            array (no clamp), and `out`'s frame is a copy of `in`'s.  FP32
+ *            storage only (EUNSUPPORTED otherwise).
  * Allocates the plan's device scratch (one grid of FP32) on the current
  * device and picks a kernel configuration (from the tuning cache when one
  * is present, otherwise built-in defaults).  Errors: EINVAL, ENOMEM,
@@ -91,6 +102,38 @@ enum stencil_storage {
  */
 STENCIL_API int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
                  const float *coeffs, int ncoeffs, int boundary);
+
+/*
+ * A plan with shared coefficients (Sec. IV.A notes that the paper's
+ * instance shares one coefficient per direction and optimises the case
+ * where all differ; the comparison codes of Sec. VI.C share them): the two
+ * neighbours at distance i along one axis share one coefficient.
+ *   axis_coeffs  host array of 1 + ndim*radius FP32 values: c_C, then for
+ *                i = 1..radius one value per axis, x, y (, z).
+ *   ncoeffs      must equal 1 + ndim*radius.
+ *   boundary     STENCIL_BOUNDARY_CLAMP (EUNSUPPORTED otherwise).
+ *   radius       1..4 (EUNSUPPORTED above).
+ * Each cell is evaluated in this fixed order, one rounding per operation:
+ * c_C*f_C, then for i = 1..radius and each axis one fused multiply-add of
+ * c_{a,i} with the rounded sum f(p - i e_a) + f(p + i e_a).  Exactly, this
+ * is Eq. (1) with c_W,i = c_E,i = c_x,i and so on; the instruction count
+ * per cell equals the per-point form's (one add replaces one FMA).  2D
+ * plans fuse up to 4 steps per pass; 3D plans run the single-step row
+ * layout.  FP32 storage.  Errors as stencil_plan.
+ */
+STENCIL_API int stencil_plan_symmetric(stencil_plan_t *plan, int ndim, const int64_t *dims,
+                                       int radius, const float *axis_coeffs, int ncoeffs,
+                                       int boundary, const char *tune);
+
+/*
+ * Expands the paper's per-direction coefficients (Sec. IV.A: one value per
+ * direction, the same for every distance) into the per-point order of
+ * stencil_plan: per_direction holds 1 + 2*ndim values c_C, c_W, c_E, c_S,
+ * c_N (, c_B, c_A); out receives 1 + 2*ndim*radius values.  Host only.
+ * Errors: EINVAL.
+ */
+STENCIL_API int stencil_coeffs_per_direction(int ndim, int radius, const float *per_direction,
+                                             float *out);
 
 /*
  * As stencil_plan, with extra controls:
@@ -118,8 +161,12 @@ STENCIL_API int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims
  *            "wl=" (lanes per tile row, 32 or 64), "vec=" (cells per lane,
  *            4, or 8 for wl=64, k=1, R <= 2, aligned rows), "nw=" (waves per
  *            workgroup, <= 16), "lz=" (planes per segment) and "pair=1" (two
- *            planes per barrier, k=1, vec=4).  E.g. "k=4,ly=256" (2D),
- *            "k=2,wl=32,nw=16,lz=64" (3D).  Unknown keys or infeasible
+ *            planes per barrier, k=1, vec=4) for the xy-tile kernel; or the
+ *            LDS-free single-step row layout: "rows=" (grid rows per
+ *            wavefront, 1, or 2 for R <= 4), "nbp=" (0/1: neighbour rows
+ *            loaded one plane ahead; rows=2 and nbp=1 need nx % 4 == 0) and
+ *            "lz=".  E.g. "k=4,ly=256" (2D), "k=2,wl=32,nw=16,lz=64",
+ *            "k=1,rows=1,nbp=1,lz=128" (3D).  Unknown keys or infeasible
  *            values give EINVAL.
  */
 STENCIL_API int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
@@ -128,8 +175,9 @@ STENCIL_API int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *d
 
 /*
  * Applies `steps` time steps to the grid at `in` and writes f^steps to `out`.
- *   in, out  device pointers to nx*ny[*nz] floats, 4-byte aligned; the two
- *            ranges must not overlap (EINVAL).  `in` is never written.
+ *   in, out  device pointers to nx*ny[*nz] floats (the padded extents for
+ *            STENCIL_BOUNDARY_PADDED), 4-byte aligned; the two ranges must
+ *            not overlap (EINVAL).  `in` is never written.
  *   steps    >= 0; 0 copies in to out.
  * Enqueues ceil(steps/K) passes on `stream`, ping-ponging between `out` and
  * the plan's scratch so that the last pass writes `out`.  A plan must not be
@@ -292,7 +340,13 @@ STENCIL_API int stencil_plan_describe(stencil_plan_t plan, char *buf, size_t len
  */
 STENCIL_API int stencil_reduce_f64(const float *x, const double *ref, int64_t n, double out[3], void *stream);
 
-/* Releases the plan and its device scratch (synchronises the device).  NULL is a no-op. */
+/*
+ * Releases the plan and its device scratch.  NULL is a no-op.  Waits for all
+ * work on the plan's device first: runs are enqueued on caller streams the
+ * plan does not record, and its scratch (and precision-form buffers) may be
+ * in use on any of them; freeing device memory (hipFree) would wait for the
+ * device anyway.  Destroy plans outside latency-critical loops.
+ */
 STENCIL_API void stencil_plan_destroy(stencil_plan_t plan);
 
 /* Static text for a status code. */

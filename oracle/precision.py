@@ -125,9 +125,16 @@ def exponents(bounds: np.ndarray) -> np.ndarray:
     return np.vectorize(tile_exponent, otypes=[np.int32])(bounds.astype(np.float64))
 
 
+def code_values(v, e):
+    """The scaled values v * 2^-e that encoding rounds to codes."""
+    return np.ldexp(np.asarray(v, dtype=np.float64), -np.asarray(e, dtype=np.int32))
+
+
 def run(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
-        threads: int = 0) -> np.ndarray:
-    """The precision form on a 3D FP32 grid; returns the FP32 result."""
+        threads: int = 0, observe=None) -> np.ndarray:
+    """The precision form on a 3D FP32 grid; returns the FP32 result.
+    observe(kind, scaled), if given, sees the scaled values of every encode
+    (kind "G" or "D"); it changes nothing."""
     c32 = np.asarray(coeffs, dtype=np.float32)
     s1 = 0.0
     for v in c32:  # summed in coefficient order, in double
@@ -146,12 +153,16 @@ def run(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
         eG = exponents(max_g)
         g16 = encode(G, per_cell(eG, shape), codec)
         gdec = decode(g16, per_cell(eG, shape), codec)
+        if observe:
+            observe("G", code_values(G, per_cell(eG, shape)))
         ddec, max_d = gdec, max_g
         for _ in range(1, w):
             bound = s1 * neighbour_max(max_d).astype(np.float64) + max_g.astype(np.float64)
             e = exponents(bound)
             v = (step(ddec) + gdec).astype(np.float32)
             max_d = tile_max(v)
+            if observe:
+                observe("D", code_values(v, per_cell(e, shape)))
             ddec = decode(encode(v, per_cell(e, shape), codec), per_cell(e, shape), codec)
         A = (A + ddec).astype(np.float32)
         t += w
@@ -159,8 +170,10 @@ def run(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
 
 
 def run_scaled(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: int,
-               threads: int = 0) -> np.ndarray:
-    """The scaled-state form on a 3D FP32 grid; returns the FP32 result."""
+               threads: int = 0, observe=None) -> np.ndarray:
+    """The scaled-state form on a 3D FP32 grid; returns the FP32 result.
+    observe(kind, scaled), if given, sees the scaled values of every encode
+    (kind "Q"); it changes nothing."""
     c32 = np.asarray(coeffs, dtype=np.float32)
     s1 = 0.0
     for v in c32:  # summed in coefficient order, in double
@@ -176,12 +189,16 @@ def run_scaled(f0: np.ndarray, coeffs, radius: int, steps: int, m: int, codec: i
         w = min(m, steps - t)
         max_q = tile_max(A)
         e = exponents(max_q)
+        if observe:
+            observe("Q", code_values(A, per_cell(e, shape)))
         qdec = decode(encode(A, per_cell(e, shape), codec), per_cell(e, shape), codec)
         for _ in range(1, w):
             bound = s1 * neighbour_max(max_q).astype(np.float64)
             e = exponents(bound)
             v = step(qdec)
             max_q = tile_max(v)
+            if observe:
+                observe("Q", code_values(v, per_cell(e, shape)))
             qdec = decode(encode(v, per_cell(e, shape), codec), per_cell(e, shape), codec)
         A = step(qdec)
         t += w

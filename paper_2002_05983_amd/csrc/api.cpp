@@ -82,9 +82,15 @@ const char *stencil_status_string(int status) {
 
 const char *stencil_last_error(void) { return g_last_error.c_str(); }
 
-int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
-                    const float *coeffs, int ncoeffs, int boundary, int storage, int anchor_m,
-                    const char *tune) {
+}  // extern "C"
+
+namespace {
+
+// Validates and builds a plan.  sym: the coefficients are shared per axis
+// and distance (1 + ndim*radius values) instead of per point.
+int plan_create(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                const float *coeffs, int ncoeffs, int boundary, int storage, int anchor_m,
+                const char *tune, bool sym) {
     g_last_error.clear();
     if (!plan) return fail(STENCIL_EINVAL, "plan pointer is NULL");
     *plan = nullptr;
@@ -92,21 +98,32 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
     if (!dims) return fail(STENCIL_EINVAL, "dims is NULL");
     if (radius < 1 || radius > 8) return fail(STENCIL_EINVAL, "radius must be 1..8 (got %d)", radius);
     if (!coeffs) return fail(STENCIL_EINVAL, "coeffs is NULL");
-    const int npts = 1 + 2 * ndim * radius;
+    const int npts = sym ? 1 + ndim * radius : 1 + 2 * ndim * radius;
     if (ncoeffs != npts)
-        return fail(STENCIL_EINVAL, "ncoeffs must be 1+2*ndim*radius = %d (got %d)", npts, ncoeffs);
-    if (boundary != STENCIL_BOUNDARY_CLAMP)
-        return fail(STENCIL_EINVAL, "unsupported boundary %d (only clamp)", boundary);
+        return fail(STENCIL_EINVAL, sym ? "ncoeffs must be 1+ndim*radius = %d (got %d)"
+                                        : "ncoeffs must be 1+2*ndim*radius = %d (got %d)",
+                    npts, ncoeffs);
+    if (boundary != STENCIL_BOUNDARY_CLAMP && boundary != STENCIL_BOUNDARY_PADDED)
+        return fail(STENCIL_EINVAL, "unknown boundary %d", boundary);
     if (storage < STENCIL_F32 || storage > STENCIL_BF16_SCALED)
         return fail(STENCIL_EINVAL, "unknown storage %d", storage);
     if (storage != STENCIL_F32 && anchor_m < 1)
         return fail(STENCIL_EINVAL, "anchor_m must be >= 1 for low-precision storage");
+    if (boundary == STENCIL_BOUNDARY_PADDED && storage != STENCIL_F32)
+        return fail(STENCIL_EUNSUPPORTED, "the padded-halo boundary is built for FP32 storage");
+    if (sym && (boundary != STENCIL_BOUNDARY_CLAMP || storage != STENCIL_F32))
+        return fail(STENCIL_EUNSUPPORTED, "shared coefficients are built for FP32 and the clamp boundary");
+    if (sym && radius > 4)
+        return fail(STENCIL_EUNSUPPORTED, "shared coefficients are built for radius 1..4");
+    // padded-halo boundary: the arrays hold the interior inside a frame of
+    // `radius` cells on every side
+    const int pad = boundary == STENCIL_BOUNDARY_PADDED ? radius : 0;
     int64_t d[3] = {1, 1, 1};
     for (int a = 0; a < ndim; ++a) {
         if (dims[a] < 1) return fail(STENCIL_EINVAL, "dims[%d] = %lld < 1", a, (long long)dims[a]);
         if (dims[a] > (int64_t)1 << 30)
             return fail(STENCIL_EUNSUPPORTED, "dims[%d] = %lld exceeds 2^30", a, (long long)dims[a]);
-        d[a] = dims[a];
+        d[a] = dims[a] + 2 * pad;
     }
     const int64_t ncells = d[0] * d[1] * d[2];  // each factor <= 2^30: check before multiplying
     if ((double)d[0] * (double)d[1] * (double)d[2] * 4.0 > 9.0e18 || ncells > ((int64_t)1 << 40))
@@ -128,6 +145,8 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
     for (int k = 0; k < npts; ++k) p->cf.c[k] = coeffs[k];
     p->storage = storage;
     p->anchor_m = anchor_m;
+    p->pad = pad;
+    p->sym = sym ? 1 : 0;
     p->serial = ++g_plan_serial;
     // the configuration is validated before any device call, so a bad
     // request reports EINVAL even where no device is present
@@ -163,6 +182,34 @@ int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int rad
     return STENCIL_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                    const float *coeffs, int ncoeffs, int boundary, int storage, int anchor_m,
+                    const char *tune) {
+    return plan_create(plan, ndim, dims, radius, coeffs, ncoeffs, boundary, storage, anchor_m,
+                       tune, false);
+}
+
+int stencil_plan_symmetric(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
+                           const float *axis_coeffs, int ncoeffs, int boundary, const char *tune) {
+    return plan_create(plan, ndim, dims, radius, axis_coeffs, ncoeffs, boundary, STENCIL_F32, 0,
+                       tune, true);
+}
+
+int stencil_coeffs_per_direction(int ndim, int radius, const float *per_direction, float *out) {
+    g_last_error.clear();
+    if (ndim != 2 && ndim != 3) return fail(STENCIL_EINVAL, "ndim must be 2 or 3 (got %d)", ndim);
+    if (radius < 1 || radius > 8) return fail(STENCIL_EINVAL, "radius must be 1..8 (got %d)", radius);
+    if (!per_direction || !out) return fail(STENCIL_EINVAL, "per_direction/out is NULL");
+    out[0] = per_direction[0];
+    for (int i = 1; i <= radius; ++i)
+        for (int d = 0; d < 2 * ndim; ++d) out[1 + (i - 1) * 2 * ndim + d] = per_direction[1 + d];
+    return STENCIL_OK;
+}
+
 int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
                  const float *coeffs, int ncoeffs, int boundary) {
     return stencil_plan_ex(plan, ndim, dims, radius, coeffs, ncoeffs, boundary, STENCIL_F32, 0,
@@ -172,6 +219,9 @@ int stencil_plan(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius
 void stencil_plan_destroy(stencil_plan_t plan) {
     if (!plan) return;
     if (plan->scratch) {
+        // runs may still use the scratch on any stream of this device (the
+        // plan does not record the caller's streams): wait for the device,
+        // as hipFree would
         (void)hipDeviceSynchronize();
         (void)hipFree(plan->scratch);
     }

@@ -689,7 +689,9 @@ int batch_create(stencil_batch_t *out, int n, const stencil_plan_t *plans, const
         const bool wide_plane = (p->ndim == 3 && p->nx * p->ny * 4 >= ((int64_t)1 << 31)) ||
                                 (p->ndim == 2 && p->nx * 4 >= ((int64_t)1 << 31));
         const bool high_radius = p->radius > 4;  // work-list kernels are built for R <= 4
-        if (steps[g] == 0 || p->storage != STENCIL_F32 || wide_plane || high_radius) {
+        // ... and for per-point coefficients with the clamp boundary
+        const bool other_form = p->pad != 0 || p->sym != 0;
+        if (steps[g] == 0 || p->storage != STENCIL_F32 || wide_plane || high_radius || other_form) {
             b->own.push_back(g);
             continue;
         }

@@ -7,9 +7,11 @@
 
 namespace star {
 
-// One step per launch, one thread per cell (reference variant).
+// One step per launch, one thread per cell (reference variant).  pad > 0:
+// padded-halo frame of that width kept fixed; sym: shared coefficients per
+// axis and distance.
 hipError_t launch_naive(int ndim, int R, const float *src, float *dst, int nx, int ny, int nz,
-                        const Coefs &cf, hipStream_t stream);
+                        const Coefs &cf, hipStream_t stream, int pad = 0, bool sym = false);
 
 // 2D x-strip / y-stream kernel fusing K steps per pass.
 struct Star2DArgs {
@@ -19,9 +21,14 @@ struct Star2DArgs {
     int K;        // steps fused in this pass (1..kMaxK2D)
     int ly;       // output rows per y-segment
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
+    int pad = 0;  // padded-halo boundary: width of the fixed frame (0 = clamp)
+    bool sym = false;  // shared coefficients per axis and distance (R <= 4, K <= 4)
     Coefs cf;
 };
 constexpr int kMaxK2D = 8;
+// Shared coefficients (one per axis and distance) are built into the 2D
+// streaming kernel for R <= 4 and K <= kMaxKSym2D fused steps.
+constexpr int kMaxKSym2D = 4;
 // Largest K built per radius: K*R <= 16 keeps the unrolled queue code and
 // its registers in budget (K = 8, 8, 5, 4, 3, 2, 2, 2 for R = 1..8).
 constexpr int max_k2d(int R) { return 16 / R < kMaxK2D ? 16 / R : kMaxK2D; }
@@ -54,6 +61,8 @@ struct Star3DArgs {
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
     int rows = 0; // LDS-free single-step layout: grid rows per wavefront (1, 2), 0 = xy tiles
     bool nbp = false;  // rows layout: neighbour rows loaded one plane ahead
+    int pad = 0;  // padded-halo boundary: width of the fixed frame (0 = clamp)
+    bool sym = false;  // shared coefficients per axis and distance (row layout, R <= 4)
     Coefs cf;
 };
 // Largest K built per radius: the tile keeps >= 8 output rows of 16 for

@@ -106,6 +106,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
     if (p->ndim == 2) {
         p->variant = STAR_S2D;
         p->K = default_k2d(R);
+        if (p->sym) p->K = std::min(p->K, kMaxKSym2D);
         p->ly = 0;
     } else {
         // defaults measured on a 512^3 grid
@@ -125,6 +126,12 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         // is 1.35x, 3.3x and 5.3x the best other single-step form at
         // R = 6, 7, 8 (the xy-tile kernel stays ahead at R <= 5)
         if (R >= 6 && p->storage == STENCIL_F32) {
+            p->s3_rpl = 1;
+            p->s3_nbp = p->nx % 4 == 0 ? 1 : 0;
+        }
+        // shared coefficients are built into the row layout only
+        if (p->sym) {
+            p->K = 1;
             p->s3_rpl = 1;
             p->s3_nbp = p->nx % 4 == 0 ? 1 : 0;
         }
@@ -198,6 +205,8 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             return star_set_error(STENCIL_EUNSUPPORTED, "2D rows must stay below 2^31 bytes");
         if (p->K < 1 || p->K > max_k2d(R))
             return star_set_error(STENCIL_EINVAL, "2D k must be in 1..16/R (at most 8)");
+        if (p->sym && p->K > kMaxKSym2D)
+            return star_set_error(STENCIL_EINVAL, "shared coefficients: 2D k must be 1..4");
         if (p->ly == 0) p->ly = default_ly(p, p->K);
         if (p->ly < 1) return star_set_error(STENCIL_EINVAL, "ly must be >= 1");
         p->vec = kVec2D;
@@ -217,6 +226,9 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         }
         if (p->K < 1 || p->K > max_k3d(R))
             return star_set_error(STENCIL_EINVAL, "3D k must be 1..4 for R = 1, 1..3 for R = 2, 3, 1..2 for R = 4..6, 1 above");
+        if (p->sym && p->s3_rpl == 0)
+            return star_set_error(STENCIL_EINVAL,
+                                  "shared coefficients in 3D run the row layout (k=1, rows=1)");
         if (p->s3_rpl > 0 || p->s3_nbp) {
             // LDS-free single-step layout: whole 256-column rows per wavefront
             if (p->s3_rpl == 0) p->s3_rpl = 1;
@@ -224,6 +236,8 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 return star_set_error(STENCIL_EINVAL, "rows= is a single-step FP32 layout (k=1, no pair)");
             if (p->s3_rpl > 2 || (p->s3_rpl == 2 && R > 4))
                 return star_set_error(STENCIL_EINVAL, "rows must be 1, or 2 for R <= 4");
+            if (p->sym && p->s3_rpl != 1)
+                return star_set_error(STENCIL_EINVAL, "shared coefficients run one row per wavefront");
             if ((p->s3_rpl == 2 || p->s3_nbp) && p->nx % 4 != 0)
                 return star_set_error(STENCIL_EINVAL, "rows=2 and nbp=1 need rows of 16 bytes (nx % 4 == 0)");
             if (p->s3_lz == 0) p->s3_lz = default_lz_rows(p);
@@ -294,7 +308,7 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
     switch (p->variant) {
         case STAR_NAIVE:
             return launch_naive(p->ndim, p->radius, src, dst, (int)p->nx, (int)p->ny, (int)p->nz,
-                                p->cf, stream);
+                                p->cf, stream, p->pad, p->sym != 0);
         case STAR_S2D: {
             Star2DArgs a;
             a.src = src;
@@ -305,6 +319,8 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
             // keep the segment length of the full passes for a tail pass
             a.ly = p->ly;
             a.aligned = (p->nx % kVec2D == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
+            a.pad = p->pad;
+            a.sym = p->sym != 0;
             a.cf = p->cf;
             switch (p->radius) {
                 case 1: return launch_star2d_r1(a, stream);
@@ -333,6 +349,8 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
             a.pair = p->s3_pair != 0 && k == 1;  // a tail pass of a K > 1 plan is not paired
             a.aligned = (p->nx % 4 == 0) && ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) == 0;
             if (a.vec == 8 && !a.aligned) a.vec = 4;
+            a.pad = p->pad;
+            a.sym = p->sym != 0;
             a.cf = p->cf;
             if (p->s3_rpl > 0 && k == 1) {
                 // LDS-free layout; grids not 16-byte aligned take its
@@ -369,6 +387,13 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
 }
 
 std::string plan_describe(const stencil_plan_s *p) {
+    std::string s = plan_describe_config(p);
+    if (p->pad) s += " boundary=padded";
+    if (p->sym) s += " coeffs=shared";
+    return s;
+}
+
+std::string plan_describe_config(const stencil_plan_s *p) {
     char buf[256];
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
     if (p->variant == STAR_S3D && p->s3_rpl > 0)

@@ -26,6 +26,8 @@ struct stencil_plan_s {
     star::Coefs cf{};
     int storage = 0;
     int anchor_m = 0;
+    int pad = 0;               // padded-halo boundary: frame width (= R); nx, ny, nz include it
+    int sym = 0;               // shared coefficients per axis and distance (cf: 1 + ndim*R values)
     int device = 0;
     uint64_t serial = 0;       // unique per plan created in this process
     float *scratch = nullptr;  // one FP32 grid, ping-pong partner of `out` (the anchor for F16/BF16)
@@ -67,6 +69,7 @@ void plan_pass_schedule(const stencil_plan_s *p, int64_t steps, std::vector<int>
 hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, float *dst,
                             hipStream_t stream);
 std::string plan_describe(const stencil_plan_s *p);
+std::string plan_describe_config(const stencil_plan_s *p);
 void plan_release_extra(stencil_plan_s *p);
 
 // Precision form (lowp.cpp): device state, and the run schedule.

@@ -14,10 +14,11 @@ namespace {
 using s2d::prefetch_rows;
 using s2d::star2d_body;
 
-template <int R, int K, int D, bool ALIGNED>
+template <int R, int K, int D, bool ALIGNED, bool SYM>
 __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ src,
                                                      float *__restrict__ dst, int nx, int ny,
-                                                     int ly, int nstrips, int nwaves, Coefs cf) {
+                                                     int ly, int nstrips, int nwaves, int pad,
+                                                     Coefs cf) {
     // Everything that does not depend on the lane is wave-uniform; the
     // readfirstlane makes the compiler keep it in scalar registers and turn
     // the per-row conditions into scalar branches.
@@ -25,13 +26,13 @@ __global__ __launch_bounds__(256) void star2d_stream(const float *__restrict__ s
                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
     const int strip = wave % nstrips, seg = wave / nstrips;
-    if (s2d::star2d_interior<R, K>(nx, ny, ly, strip, seg))
-        star2d_body<R, K, D, ALIGNED, false>(src, dst, nx, ny, ly, strip, seg, cf);
+    if (s2d::star2d_interior<R, K>(nx, ny, ly, strip, seg, pad))
+        star2d_body<R, K, D, ALIGNED, false, SYM>(src, dst, nx, ny, ly, strip, seg, cf);
     else
-        star2d_body<R, K, D, ALIGNED, true>(src, dst, nx, ny, ly, strip, seg, cf);
+        star2d_body<R, K, D, ALIGNED, true, SYM>(src, dst, nx, ny, ly, strip, seg, cf, pad);
 }
 
-template <int K, bool AL>
+template <int K, bool AL, bool SYM>
 hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
     constexpr int TX = star2d_tile_x(K, STAR_R);
     const int nstrips = (a.nx + TX - 1) / TX;
@@ -41,8 +42,9 @@ hipError_t launch_k(const Star2DArgs &a, hipStream_t stream) {
     // one row is one buffer descriptor: its byte size and masked offsets stay below 2^31
     if ((int64_t)a.nx * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    hipLaunchKernelGGL((star2d_stream<STAR_R, K, prefetch_rows<STAR_R, K>(), AL>), dim3(blocks), dim3(256), 0, stream, a.src,
-                       a.dst, a.nx, a.ny, a.ly, nstrips, (int)nwaves, a.cf);
+    hipLaunchKernelGGL((star2d_stream<STAR_R, K, prefetch_rows<STAR_R, K>(), AL, SYM>), dim3(blocks),
+                       dim3(256), 0, stream, a.src, a.dst, a.nx, a.ny, a.ly, nstrips, (int)nwaves,
+                       a.pad, a.cf);
     return hipGetLastError();
 }
 
@@ -51,7 +53,12 @@ hipError_t launch_al(const Star2DArgs &a, hipStream_t stream) {
     if constexpr (K > max_k2d(STAR_R)) {
         return hipErrorInvalidValue;
     } else {
-        return a.aligned ? launch_k<K, true>(a, stream) : launch_k<K, false>(a, stream);
+        if (a.sym) {
+            if constexpr (STAR_R <= 4 && K <= kMaxKSym2D)
+                return a.aligned ? launch_k<K, true, true>(a, stream) : launch_k<K, false, true>(a, stream);
+            return hipErrorInvalidValue;
+        }
+        return a.aligned ? launch_k<K, true, false>(a, stream) : launch_k<K, false, false>(a, stream);
     }
 }
 

@@ -44,7 +44,10 @@ constexpr int VEC = kVec2D;
 // the wavefront take their own outermost cell as the missing neighbour;
 // otherwise those lanes hold halo columns whose values never reach the
 // output and the shifts fill them with zero.
-template <int R, int NS, int CS, bool EDGE>
+// SYM: shared coefficients, one per axis and distance (cf holds c_C, then
+// c_x,i, c_y,i for i = 1..R): per distance, one FMA with the rounded sum of
+// the W and E cells, then one with the sum of the S and N cells.
+template <int R, int NS, int CS, bool EDGE, bool SYM = false>
 __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
                                            float (&res)[VEC]) {
     static_assert(R <= 2 * VEC, "x-neighbours come from the lanes at most two away");
@@ -75,10 +78,15 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
             const float ea = (e + i < VEC) ? q[CS][e + i] : right[e + i - VEC + 1];
             const float s = q[(CS - i + NS) % NS][e];
             const float n = q[(CS + i) % NS][e];
-            acc = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], w, acc);
-            acc = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], ea, acc);
-            acc = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], s, acc);
-            acc = __builtin_fmaf(cf.c[coef_index<2>(kN, i)], n, acc);
+            if constexpr (SYM) {
+                acc = __builtin_fmaf(cf.c[1 + 2 * (i - 1)], w + ea, acc);
+                acc = __builtin_fmaf(cf.c[2 + 2 * (i - 1)], s + n, acc);
+            } else {
+                acc = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], w, acc);
+                acc = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], ea, acc);
+                acc = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], s, acc);
+                acc = __builtin_fmaf(cf.c[coef_index<2>(kN, i)], n, acc);
+            }
         }
         res[e] = acc;
     }
@@ -90,10 +98,15 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
 // columns and every row its stages touch lie inside the grid
 // (star2d_interior), so no clamp is ever applied and the border code is
 // left out; for such a strip it computes the same bits as the general form.
-template <int R, int K, int D, bool ALIGNED, bool EDGE = true>
+// pad > 0: padded-halo boundary (Sec. IV.B): the grid is the padded array
+// and its frame of `pad` cells is fixed, so in the general form every stage
+// gives a frame cell its own (unchanged) value; the interior form never
+// holds a frame cell among the cells that reach the output (the interior
+// test is shrunk by the frame).
+template <int R, int K, int D, bool ALIGNED, bool EDGE = true, bool SYM = false>
 __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float *__restrict__ dst,
                                             int nx, int ny, int ly, int strip, int seg,
-                                            const Coefs &cf) {
+                                            const Coefs &cf, int pad = 0) {
     constexpr int P = 2 * R + 1;  // rows a stage keeps: its y-window
     constexpr int NQ = P + D;     // input ring: y-window plus D rows in flight
     // stage s >= 2 keeps its window in slot (ring slot mod P), which follows
@@ -192,9 +205,27 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
             const int r = j - S * R;  // row produced by stage S
             float res[VEC];
             if constexpr (S == 1)
-                star2d_row<R, NQ, (PH - R + NQ) % NQ, EDGE>(q0, cf, res);
+                star2d_row<R, NQ, (PH - R + NQ) % NQ, EDGE, SYM>(q0, cf, res);
             else
-                star2d_row<R, P, (PH % P - R + P) % P, EDGE>(q[S - 2], cf, res);
+                star2d_row<R, P, (PH % P - R + P) % P, EDGE, SYM>(q[S - 2], cf, res);
+            if constexpr (EDGE) {
+                if (pad > 0) {
+                    // the fixed frame of the padded array keeps its values:
+                    // a frame cell takes its centre (this stage's input)
+                    const bool frame_row = r < pad || r >= ny - pad;
+                    auto keep_frame = [&](const float (&ctr)[VEC]) STAR_INLINE {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const int c = col0 + e;
+                            res[e] = (frame_row || c < pad || c >= nx - pad) ? ctr[e] : res[e];
+                        }
+                    };
+                    if constexpr (S == 1)
+                        keep_frame(q0[(PH - R + NQ) % NQ]);
+                    else
+                        keep_frame(q[S - 2][(PH % P - R + P) % P]);
+                }
+            }
             if constexpr (S < K) {
                 constexpr int W = PH % P;  // slot of this row in the stage's window
                 if constexpr (EDGE) {
@@ -248,13 +279,17 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
 
 // True when strip `strip` of segment `seg` needs no clamp at any stage: its
 // 64*VEC columns lie inside the grid, and rows y0-2KR .. y1-1+KR (the rows
-// its stages read and produce) do too.
+// its stages read and produce) do too.  With a padded-halo frame of `pad`
+// cells the same must hold inside the frame, so that no frame cell is
+// updated.
 template <int R, int K>
-__device__ __forceinline__ bool star2d_interior(int nx, int ny, int ly, int strip, int seg) {
+__device__ __forceinline__ bool star2d_interior(int nx, int ny, int ly, int strip, int seg,
+                                                int pad = 0) {
     const int xs = strip * star2d_tile_x(K, R) - star2d_halo(K, R);
     const int y0 = seg * ly;
     const int y1 = min(y0 + ly, ny);
-    return xs >= 0 && xs + 64 * VEC <= nx && y0 > 2 * K * R && y1 + K * R <= ny;
+    return xs >= pad && xs + 64 * VEC <= nx - pad && y0 > 2 * K * R + pad &&
+           y1 + K * R <= ny - pad;
 }
 
 // Rows in flight per wavefront: two y-windows for the memory-bound small-K

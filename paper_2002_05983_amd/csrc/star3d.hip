@@ -18,16 +18,16 @@ template <int R, int K, int VEC, int WL, int D, bool ALIGNED, bool PAIR>
 __global__ __launch_bounds__(1024) void star3d_stream(const float *__restrict__ src,
                                                       float *__restrict__ dst, int nx, int ny,
                                                       int nz, int hx, int tx, int ntx, int nty,
-                                                      int lz, Coefs cf) {
+                                                      int lz, int pad, Coefs cf) {
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int strip = lb % ntx, ytile = (lb / ntx) % nty, zseg = lb / (ntx * nty);
     const int nt = (blockDim.x >> 6) * (64 / WL);
-    if (s3d::star3d_interior<R, K, VEC, WL>(nx, ny, nz, hx, tx, strip, ytile, zseg, lz, nt))
+    if (s3d::star3d_interior<R, K, VEC, WL>(nx, ny, nz, hx, tx, strip, ytile, zseg, lz, nt, pad))
         star3d_body<R, K, VEC, WL, D, ALIGNED, false, PAIR>(src, dst, nx, ny, nz, hx, tx, strip,
                                                             ytile, zseg, lz, cf);
     else
         star3d_body<R, K, VEC, WL, D, ALIGNED, true, PAIR>(src, dst, nx, ny, nz, hx, tx, strip,
-                                                           ytile, zseg, lz, cf);
+                                                           ytile, zseg, lz, cf, pad);
 }
 
 template <int K, int VEC, int WL, bool AL, bool PAIR = false>
@@ -57,7 +57,7 @@ hipError_t launch_k3(const Star3DArgs &a, hipStream_t stream) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(nw * 64), lds, stream, a.src, a.dst,
-                       a.nx, a.ny, a.nz, hx, tx, ntx, nty, a.lz, a.cf);
+                       a.nx, a.ny, a.nz, hx, tx, ntx, nty, a.lz, a.pad, a.cf);
     return hipGetLastError();
 }
 
@@ -95,6 +95,7 @@ hipError_t launch_kv(const Star3DArgs &a, hipStream_t stream) {
 
 hipError_t STAR_CAT(launch_star3d_r, STAR_R)(const Star3DArgs &a, hipStream_t stream) {
     if (a.lz < 1 || a.nx < 1 || a.ny < 1 || a.nz < 1) return hipErrorInvalidValue;
+    if (a.sym) return hipErrorInvalidValue;  // shared coefficients run the row layout
     switch (a.K) {
         case 1: return launch_kv<1>(a, stream);
         case 2: return launch_kv<2>(a, stream);

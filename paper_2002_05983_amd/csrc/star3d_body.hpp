@@ -70,10 +70,15 @@ __device__ __forceinline__ void lds_read_row(const float *row, int lr, float (&v
 // PAIR (single-step passes only): two planes per barrier -- both centre
 // rows go to LDS (four buffers), then both planes are computed -- which
 // halves the barriers and the per-plane synchronisation; the same bits.
+// pad > 0: padded-halo boundary (Sec. IV.B): the grid is the padded array
+// and its frame of `pad` cells is fixed; in the general form every stage
+// gives a frame cell its own (unchanged) value, and the interior test
+// (star3d_interior) keeps frame cells out of the interior form.
 template <int R, int K, int VEC, int WL, int D, bool ALIGNED, bool EDGE = true, bool PAIR = false>
 __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float *__restrict__ dst,
                                             int nx, int ny, int nz, int hx, int tx, int strip,
-                                            int ytile, int zseg, int lz, const Coefs &cf) {
+                                            int ytile, int zseg, int lz, const Coefs &cf,
+                                            int pad = 0) {
     static_assert(!PAIR || K == 1, "two planes per barrier: single-step passes only");
     constexpr int P = 2 * R + 1;      // planes a stage keeps: its z-window
     // Single-step passes load straight into an input ring of the window plus
@@ -259,6 +264,21 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             load_plane(zstart + decltype(phc)::value, q0[decltype(phc)::value]);
     });
 
+    // Padded-halo frame: a frame cell of plane r keeps its centre value ctr.
+    const bool frame_row = y < pad || y >= ny - pad;
+    auto keep_frame = [&](int r, const float (&ctr)[VEC], float (&res)[VEC]) STAR_INLINE {
+        if constexpr (EDGE) {
+            if (pad > 0) {
+                const bool frame = frame_row || r < pad || r >= nz - pad;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int c = col0 + e;
+                    res[e] = (frame || c < pad || c >= nx - pad) ? ctr[e] : res[e];
+                }
+            }
+        }
+    };
+
     // The output row of plane r (stage K), masked to the tile and grid.
     auto store_row = [&](int r, const float (&res)[VEC]) STAR_INLINE {
         // one descriptor per plane (wave-uniform); the row goes into the
@@ -318,13 +338,16 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
                 if (n < 2 * S * R || !computes(S)) return;
                 const int r = zl - S * R;  // plane produced by stage S
                 float res[VEC];
-                if constexpr (S == 1)
+                if constexpr (S == 1) {
                     cells(std::integral_constant<int, NQ>{},
                           std::integral_constant<int, (PH - R + NQ) % NQ>{}, q0, 0, b, res);
-                else
+                    keep_frame(r, q0[(PH - R + NQ) % NQ], res);
+                } else {
                     cells(std::integral_constant<int, P>{},
                           std::integral_constant<int, (PS - R + P) % P>{}, q[S - 2], S - 1, b,
                           res);
+                    keep_frame(r, q[S - 2][(PS - R + P) % P], res);
+                }
                 if constexpr (S < K) {
                     constexpr int WS = PS;
                     if constexpr (EDGE) {
@@ -375,6 +398,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             float res[VEC];
             cells(std::integral_constant<int, NQ>{}, std::integral_constant<int, (PH0 - R + NQ) % NQ>{},
                   q0, 0, b, res);
+            keep_frame(zl - R, q0[(PH0 - R + NQ) % NQ], res);
             store_row(zl - R, res);
         }
         // one plane at a time: interleaving the two would raise the
@@ -384,6 +408,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             float res[VEC];
             cells(std::integral_constant<int, NQ>{}, std::integral_constant<int, (PH1 - R + NQ) % NQ>{},
                   q0, 0, b + 1, res);
+            keep_frame(zl + 1 - R, q0[(PH1 - R + NQ) % NQ], res);
             store_row(zl + 1 - R, res);
         }
     };
@@ -414,14 +439,14 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
 // stages read and produce all lie inside the grid.
 template <int R, int K, int VEC, int WL>
 __device__ __forceinline__ bool star3d_interior(int nx, int ny, int nz, int hx, int tx, int strip,
-                                                int ytile, int zseg, int lz, int nt) {
+                                                int ytile, int zseg, int lz, int nt, int pad = 0) {
     const int xs = strip * tx - hx;
     const int ty = nt - 2 * K * R;
     const int y0 = ytile * ty - K * R;
     const int z0 = zseg * lz;
     const int z1 = min(z0 + lz, nz);
-    return hx > 0 && xs >= 0 && xs + WL * VEC <= nx && y0 >= 0 && y0 + nt <= ny &&
-           z0 > 2 * K * R && z1 + K * R <= nz;
+    return hx > 0 && xs >= pad && xs + WL * VEC <= nx - pad && y0 >= pad && y0 + nt <= ny - pad &&
+           z0 > 2 * K * R + pad && z1 + K * R <= nz - pad;
 }
 
 // Prefetch depth (planes) per configuration, sized so that a 1024-thread

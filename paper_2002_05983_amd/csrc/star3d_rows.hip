@@ -22,11 +22,11 @@ using s3r::star3d_rows_body;
 // XCD-aware block order, one L2) hold neighbouring strips and row blocks
 // at the same planes, so the y-neighbour rows they load from each other
 // are cache hits.  WPE: waves per SIMD the register budget is sized for.
-template <int R, int RPL, bool NBP, bool AL, int WPE>
+template <int R, int RPL, bool NBP, bool AL, int WPE, bool SYM>
 __global__ __launch_bounds__(256, WPE) void star3d_rows(const float *__restrict__ src,
                                                         float *__restrict__ dst, int nx, int ny,
                                                         int nz, int nstrips, int nyb, int lz,
-                                                        int nwaves, Coefs cf) {
+                                                        int nwaves, int pad, Coefs cf) {
     const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 +
                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
@@ -35,14 +35,14 @@ __global__ __launch_bounds__(256, WPE) void star3d_rows(const float *__restrict_
     const int zseg = wave / (nstrips * nyb);
     constexpr int D = prefetch_rows3<R, RPL>();
     if (AL && (strip + 1) * STRIP > nx)
-        star3d_rows_body<R, RPL, D, NBP, AL, true>(src, dst, nx, ny, nz, strip, yb * RPL,
-                                                   zseg * lz, lz, cf);
+        star3d_rows_body<R, RPL, D, NBP, AL, true, SYM>(src, dst, nx, ny, nz, strip, yb * RPL,
+                                                        zseg * lz, lz, cf, pad);
     else
-        star3d_rows_body<R, RPL, D, NBP, AL, false>(src, dst, nx, ny, nz, strip, yb * RPL,
-                                                    zseg * lz, lz, cf);
+        star3d_rows_body<R, RPL, D, NBP, AL, false, SYM>(src, dst, nx, ny, nz, strip, yb * RPL,
+                                                         zseg * lz, lz, cf, pad);
 }
 
-template <int RPL, bool NBP, bool AL>
+template <int RPL, bool NBP, bool AL, bool SYM = false>
 hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
     const int nstrips = (a.nx + STRIP - 1) / STRIP;
     const int nyb = (a.ny + RPL - 1) / RPL;
@@ -56,8 +56,9 @@ hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
     constexpr int R = STAR_R;
     constexpr int WPE = (RPL == 1 && (R <= 3 || (R == 4 && AL && !NBP))) ? 4 : 2;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    hipLaunchKernelGGL((star3d_rows<STAR_R, RPL, NBP, AL, WPE>), dim3(blocks), dim3(256), 0, stream,
-                       a.src, a.dst, a.nx, a.ny, a.nz, nstrips, nyb, a.lz, (int)nwaves, a.cf);
+    hipLaunchKernelGGL((star3d_rows<STAR_R, RPL, NBP, AL, WPE, SYM>), dim3(blocks), dim3(256), 0,
+                       stream, a.src, a.dst, a.nx, a.ny, a.nz, nstrips, nyb, a.lz, (int)nwaves,
+                       a.pad, a.cf);
     return hipGetLastError();
 }
 
@@ -68,6 +69,15 @@ hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
 
 hipError_t STAR_CAT(launch_star3d_rows_r, STAR_R)(const Star3DArgs &a, hipStream_t stream) {
     if (a.lz < 1 || a.nx < 1 || a.ny < 1 || a.nz < 1 || a.K != 1) return hipErrorInvalidValue;
+    if (a.sym) {
+        // shared coefficients: one row per wavefront, radius <= 4
+        if constexpr (STAR_R <= 4) {
+            if (!a.aligned) return launch_rows<1, false, false, true>(a, stream);
+            return a.nbp ? launch_rows<1, true, true, true>(a, stream)
+                         : launch_rows<1, false, true, true>(a, stream);
+        }
+        return hipErrorInvalidValue;
+    }
     if (!a.aligned) {
         if (a.rows != 1 || a.nbp) return hipErrorInvalidValue;  // built for one row, no prefetch
         return launch_rows<1, false, false>(a, stream);

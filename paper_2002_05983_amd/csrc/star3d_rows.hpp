@@ -44,11 +44,16 @@ constexpr int STRIP = 64 * VEC;  // columns per wavefront strip
 // z0 .. min(z0+lz, nz)-1.  Every argument is wave-uniform.
 // NBP: the y-neighbour rows and the halo of the next centre plane are
 // loaded one plane ahead (more registers, latency off the critical path).
-template <int R, int RPL, int D, bool NBP, bool ALIGNED, bool RAGGED>
+// SYM: shared coefficients, one per axis and distance (cf holds c_C, then
+// c_x,i, c_y,i, c_z,i for i = 1..R): per distance and axis one FMA with the
+// rounded sum of the pair of cells.
+// pad > 0: padded-halo boundary (Sec. IV.B): the grid is the padded array
+// and the cells of its frame of `pad` cells keep their values.
+template <int R, int RPL, int D, bool NBP, bool ALIGNED, bool RAGGED, bool SYM = false>
 __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
                                                  float *__restrict__ dst, int nx, int ny, int nz,
                                                  int strip, int rows0, int z0, int lz,
-                                                 const Coefs &cf) {
+                                                 const Coefs &cf, int pad = 0) {
     constexpr int P = 2 * R + 1;       // z-window planes
     constexpr int NQ = P + D;          // ring: window plus D planes in flight
     constexpr int HW = R > 4 ? 8 : 4;  // halo cells per side
@@ -203,16 +208,36 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
             for (int e = 0; e < VEC; ++e) {
                 const float wv = (e - i >= 0) ? c[e - i] : left[i - e];
                 const float ev = (e + i < VEC) ? c[e + i] : right[e + i - VEC + 1];
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kW, i)], wv, acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kE, i)], ev, acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kS, i)], sv[e], acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kN, i)], nv[e], acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kB, i)], q[(CS - i + NQ) % NQ][k][e], acc[e]);
-                acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kA, i)], q[(CS + i) % NQ][k][e], acc[e]);
+                const float bv = q[(CS - i + NQ) % NQ][k][e], av = q[(CS + i) % NQ][k][e];
+                if constexpr (SYM) {
+                    acc[e] = __builtin_fmaf(cf.c[1 + 3 * (i - 1)], wv + ev, acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[2 + 3 * (i - 1)], sv[e] + nv[e], acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[3 + 3 * (i - 1)], bv + av, acc[e]);
+                } else {
+                    acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kW, i)], wv, acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kE, i)], ev, acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kS, i)], sv[e], acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kN, i)], nv[e], acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kB, i)], bv, acc[e]);
+                    acc[e] = __builtin_fmaf(cf.c[coef_index<3>(kA, i)], av, acc[e]);
+                }
             }
         }
 #pragma unroll
         for (int e = 0; e < VEC; ++e) res[e] = acc[e];
+    };
+
+    // Padded-halo frame: a frame cell of plane r, own row k keeps its centre.
+    auto keep_frame = [&](int r, int k, const float (&ctr)[VEC], float (&res)[VEC]) STAR_INLINE {
+        if (pad > 0) {
+            const int yy = rows0 + k;
+            const bool frame = r < pad || r >= nz - pad || yy < pad || yy >= ny - pad;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int cc = col0 + e;
+                res[e] = (frame || cc < pad || cc >= nx - pad) ? ctr[e] : res[e];
+            }
+        }
     };
 
     auto store_row = [&](int r, int k, const float (&res)[VEC]) STAR_INLINE {
@@ -258,6 +283,7 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
         for (int k = 0; k < RPL; ++k) {
             float res[VEC];
             cells(std::integral_constant<int, CS>{}, k, std::integral_constant<int, B>{}, res);
+            keep_frame(r, k, q[CS][k], res);
             store_row(r, k, res);
         }
     };

@@ -54,9 +54,9 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
     const int R = p->radius;
     char buf[96];
     if (p->ndim == 3 && R > 4 && p->storage == STENCIL_F32)
-        out.push_back("naive");  // competitive with the spilling 3D kernel above radius 4
+        out.push_back("naive");  // the one-thread-per-cell kernel, timed above radius 4
     if (p->ndim == 2) {
-        for (int K = 1; K <= max_k2d(R); ++K)
+        for (int K = 1; K <= (p->sym ? kMaxKSym2D : max_k2d(R)); ++K)
             for (int ly : {64, 96, 128, 192, 256, 384}) {
                 if (ly > p->ny && ly != 64) continue;
                 snprintf(buf, sizeof buf, "k=%d,ly=%d", K, ly);
@@ -68,7 +68,7 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
             // prefetch, segment length
             for (int rows : {1, 2})
                 for (int nbp : {0, 1}) {
-                    if (rows == 2 && R > 4) continue;
+                    if (rows == 2 && (R > 4 || p->sym)) continue;
                     if ((rows == 2 || nbp) && p->nx % 4 != 0) continue;
                     for (int lz : {32, 64, 128, 256}) {
                         if (lz > p->nz && lz != 32) continue;
@@ -77,7 +77,8 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                     }
                 }
         }
-        const int kmax = p->storage == STENCIL_F32 ? max_k3d(R) : 1;
+        // shared coefficients in 3D run the row layout only
+        const int kmax = p->sym ? 0 : p->storage == STENCIL_F32 ? max_k3d(R) : 1;
         for (int K = 1; K <= kmax; ++K)
             for (int wl : {64, 32})
                 for (int vec : {4, 8}) {

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstencil_mi355x.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EOVERFLOW = 0, -1, -2, -3, -4, -5
-BOUNDARY_CLAMP = 0
+BOUNDARY_CLAMP, BOUNDARY_PADDED = 0, 1
+BOUNDARY = {"clamp": BOUNDARY_CLAMP, "padded": BOUNDARY_PADDED}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "f16-scaled": 3, "bf16-scaled": 4}
 
 _lib = None
@@ -30,6 +31,9 @@ SIGNATURES = {
     "stencil_plan_ex": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _i64p, ctypes.c_int, _fp,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_char_p]),
+    "stencil_plan_symmetric": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _i64p, ctypes.c_int,
+                                              _fp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p]),
+    "stencil_coeffs_per_direction": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _fp, _fp]),
     "stencil_run": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "stencil_run_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "stencil_run_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -108,25 +112,38 @@ def _check_grid(t, ncells: int, name: str):
 
 class Plan:
     """A star-stencil plan: grid shape (numpy/torch order, slowest axis first),
-    radius and per-point coefficients (centre, then W,E,S,N[,B,A] per distance)."""
+    radius and per-point coefficients (centre, then W,E,S,N[,B,A] per distance).
+
+    boundary "padded": `shape` is the interior; the tensors the plan runs on
+    hold shape[a] + 2*radius cells per axis (a fixed ghost frame).
+    symmetric: coeffs are shared per axis and distance (c_C, then x, y[, z]
+    for each distance: stencil_plan_symmetric)."""
 
     def __init__(self, shape, radius: int, coeffs, storage: str = "f32", anchor_m: int = 0,
-                 tune: str | None = None):
+                 tune: str | None = None, boundary: str = "clamp", symmetric: bool = False):
         L = load()
         shape = tuple(int(s) for s in shape)
         self.shape = shape
         self.ndim = len(shape)
         self.radius = int(radius)
+        pad = self.radius if boundary == "padded" else 0
+        self.array_shape = tuple(s + 2 * pad for s in shape)
         self.ncells = 1
-        for s in shape:
+        for s in self.array_shape:
             self.ncells *= s
         dims = (ctypes.c_int64 * self.ndim)(*shape[::-1])
         c = [float(v) for v in coeffs]
         carr = (ctypes.c_float * max(1, len(c)))(*c)
         h = _vp()
-        rc = L.stencil_plan_ex(ctypes.byref(h), self.ndim, dims, self.radius, carr, len(c),
-                               BOUNDARY_CLAMP, STORAGE[storage], int(anchor_m),
-                               tune.encode() if tune else None)
+        if symmetric:
+            if storage != "f32" or anchor_m:
+                raise ValueError("shared coefficients are built for FP32 storage")
+            rc = L.stencil_plan_symmetric(ctypes.byref(h), self.ndim, dims, self.radius, carr,
+                                          len(c), BOUNDARY[boundary], tune.encode() if tune else None)
+        else:
+            rc = L.stencil_plan_ex(ctypes.byref(h), self.ndim, dims, self.radius, carr, len(c),
+                                   BOUNDARY[boundary], STORAGE[storage], int(anchor_m),
+                                   tune.encode() if tune else None)
         _check(rc)
         self._h = h
 
@@ -265,6 +282,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def coeffs_per_direction(ndim: int, radius: int, per_direction):
+    """The per-point coefficients of a star whose coefficient is one per
+    direction (c_C, c_W, c_E, c_S, c_N[, c_B, c_A]), as stencil_plan takes
+    them (stencil_coeffs_per_direction)."""
+    src = (ctypes.c_float * (1 + 2 * ndim))(*[float(v) for v in per_direction])
+    out = (ctypes.c_float * (1 + 2 * ndim * radius))()
+    _check(load().stencil_coeffs_per_direction(int(ndim), int(radius), src, out))
+    return [out[k] for k in range(1 + 2 * ndim * radius)]
 
 
 def reduce_f64(x, ref=None, stream=None):

@@ -46,7 +46,7 @@ def cases():
     out = {}
     for r in (1, 2, 3, 4):
         out[f"2d16k_r{r}"] = dict(ndim=2, dims=(16384, 16384), radius=r, steps=1000,
-                                  grid=("uniform", 1), coef=1000 + r, random=768)
+                                  grid=("uniform", 1), coef=1000 + r, random=900)
     for r in (1, 2, 3, 4):
         out[f"3d512_r{r}"] = dict(ndim=3, dims=(512, 512, 512), radius=r, steps=200,
                                   grid=("uniform", 2), coef=2000 + r, random=768)

@@ -75,7 +75,7 @@ def _plan(lib, ndim, dims, radius, coeffs, ncoeffs=None, boundary=0, storage=0, 
     dict(ndim=3, dims=[4, 4, 4], radius=2, coeffs=[0.0] * 9),
     dict(ndim=2, dims=[0, 4], radius=1, coeffs=[0.0] * 5),
     dict(ndim=2, dims=[4, -3], radius=1, coeffs=[0.0] * 5),
-    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, boundary=1),
+    dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, boundary=2),
     dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, storage=7),
     dict(ndim=2, dims=[4, 4], radius=1, coeffs=[0.0] * 5, storage=1, anchor=0),
     dict(ndim=2, dims=[4, 4], radius=1, coeffs=[float("nan")] + [0.0] * 4),
@@ -201,3 +201,62 @@ def test_2d_row_limit_is_checked_before_the_device(lib):
     rc, h = _plan(lib, 2, [(1 << 29) + 1, 2], 1, c)
     assert rc == -4 and not h.value, (rc, lib.stencil_last_error())
     assert b"2^31" in lib.stencil_last_error()
+
+
+def test_coeffs_per_direction_expands_by_hand(lib):
+    """One value per direction (Sec. IV.A's instance) expands to the same
+    value at every distance, in the per-point order."""
+    src = (ctypes.c_float * 7)(0.4, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6)
+    out = (ctypes.c_float * 13)()
+    assert lib.stencil_coeffs_per_direction(3, 2, src, out) == 0
+    want = [0.4] + [0.1, 0.2, 0.3, 0.4, 0.5, 0.6] * 2
+    assert [round(v, 6) for v in out] == [round(v, 6) for v in want]
+    src2 = (ctypes.c_float * 5)(1, 2, 3, 4, 5)
+    out2 = (ctypes.c_float * 13)()
+    assert lib.stencil_coeffs_per_direction(2, 3, src2, out2) == 0
+    assert list(out2) == [1.0] + [2.0, 3.0, 4.0, 5.0] * 3
+    assert lib.stencil_coeffs_per_direction(4, 1, src, out) == -1
+    assert lib.stencil_coeffs_per_direction(2, 0, src, out) == -1
+    assert lib.stencil_coeffs_per_direction(2, 1, None, out) == -1
+
+
+def _plan_sym(lib, ndim, dims, radius, coeffs, boundary=0, tune=None):
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int64 * ndim)(*dims)
+    c = (ctypes.c_float * max(1, len(coeffs)))(*coeffs)
+    rc = lib.stencil_plan_symmetric(ctypes.byref(h), ndim, d, radius, c, len(coeffs), boundary,
+                                    tune)
+    return rc, h
+
+
+@pytest.mark.parametrize("ndim,radius,ncoef,boundary,tune,want", [
+    (2, 2, 5, 0, None, (0, -3)),
+    (2, 2, 9, 0, None, (-1,)),        # per-point count is not the shared count
+    (3, 3, 10, 0, None, (0, -3)),
+    (3, 5, 16, 0, None, (-4,)),       # built for radius 1..4
+    (2, 2, 5, 1, None, (-4,)),        # clamp boundary only
+    (2, 2, 5, 7, None, (-1,)),
+    (2, 2, 5, 0, b"k=4,ly=64", (0, -3)),
+    (2, 2, 5, 0, b"k=5", (-1,)),      # up to 4 fused steps
+    (3, 2, 7, 0, b"k=2", (-1,)),      # 3D runs the single-step row layout
+    (3, 2, 7, 0, b"k=1,wl=32,nw=16", (-1,)),
+    (3, 2, 7, 0, b"k=1,rows=1,nbp=1,lz=64", (0, -3)),
+    (3, 2, 7, 0, b"k=1,rows=2", (-1,)),
+])
+def test_symmetric_plan_validation(lib, ndim, radius, ncoef, boundary, tune, want):
+    rc, h = _plan_sym(lib, ndim, [64] * ndim, radius, [0.1] * ncoef, boundary, tune)
+    assert rc in want, (rc, lib.stencil_last_error())
+    if rc == 0:
+        lib.stencil_plan_destroy(h)
+
+
+def test_padded_boundary_validation(lib):
+    c = [0.1] * 13
+    rc, h = _plan(lib, 3, [16, 16, 16], 2, c, boundary=1)
+    assert rc in (0, -3), lib.stencil_last_error()
+    if rc == 0:
+        lib.stencil_plan_destroy(h)
+    rc, h = _plan(lib, 3, [16, 16, 16], 2, c, boundary=1, storage=1, anchor=4)
+    assert rc == -4 and b"padded" in lib.stencil_last_error()
+    rc, h = _plan(lib, 2, [16, 16], 2, [0.1] * 9, boundary=2)
+    assert rc == -1

@@ -1,0 +1,217 @@
+"""GPU parity of the padded-halo boundary and of shared coefficients.
+
+Padded halo (Sec. IV.B): the plan runs on arrays that hold the interior
+inside a fixed ghost frame of R cells; compared bit for bit with the
+oracle's padded form (star_run_padded, FP32 order) for every kernel that
+runs it -- the 2D streaming kernel at every K, the 3D xy-tile kernel at
+every K, the 3D row layout, the one-thread-per-cell kernel -- with random
+frame values, sides of one cell and ragged strips.
+
+Shared coefficients (one per axis and distance): compared bit for bit with
+the oracle's shared FP32 order (star_run_sym_f32) in the 2D streaming
+kernel (K <= 4), the 3D row layout and the one-thread-per-cell kernel, and
+within the FP32 tolerance of the FP64 definition with the coefficients
+expanded per point.
+"""
+import numpy as np
+import pytest
+
+from paper_2002_05983_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def st():
+    from paper_2002_05983_amd import stencil
+    stencil.load()
+    return stencil
+
+
+def run(torch, st, f, shape, radius, coeffs, steps, **kw):
+    plan = st.Plan(shape, radius, coeffs, **kw)
+    assert tuple(f.shape) == plan.array_shape
+    x = torch.from_numpy(f).cuda()
+    y = torch.full_like(x, float("nan"))
+    plan.run(x, y, steps)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy()
+    assert np.array_equal(x.cpu().numpy(), f)
+    desc = plan.describe()
+    plan.close()
+    return out, desc
+
+
+def assert_bitwise(got, want, what):
+    if not np.array_equal(got.view(np.uint32), want.view(np.uint32)):
+        bad = np.argwhere(got.view(np.uint32) != want.view(np.uint32))
+        raise AssertionError(f"{what}: {len(bad)} cells differ, first at {bad[:5].tolist()}, "
+                             f"got {got[tuple(bad[0])]!r} want {want[tuple(bad[0])]!r}")
+
+
+# interior shapes (slowest axis first)
+PAD2D = [(1, 1), (3, 5), (17, 33), (40, 300), (64, 700), (9, 256)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("shape", PAD2D)
+def test_padded_2d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    c = synth.coefficients(1100 + radius, 2, radius)
+    f = synth.grid_uniform(1200 + radius, tuple(n + 2 * radius for n in shape))
+    cache = {}
+    for K in (1, 2, 3, 4, 8):
+        if K * radius > 16:
+            continue
+        for ly in (7, 64):
+            steps = 2 * K + 1
+            if steps not in cache:
+                cache[steps] = oracle_mod.star_run_padded(f, c, radius, steps, dtype=np.float32)
+            got, desc = run(torch, st, f, shape, radius, c, steps, boundary="padded",
+                            tune=f"k={K},ly={ly}")
+            assert "boundary=padded" in desc
+            assert_bitwise(got, cache[steps], f"padded 2D {shape} r{radius} [{desc}]")
+    got, desc = run(torch, st, f, shape, radius, c, 3, boundary="padded", tune="naive")
+    assert_bitwise(got, oracle_mod.star_run_padded(f, c, radius, 3, dtype=np.float32),
+                   f"padded 2D naive {shape} r{radius}")
+
+
+PAD3D = [(1, 1, 1), (3, 2, 5), (9, 17, 33), (20, 37, 300), (6, 3, 257), (11, 9, 256)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", PAD3D)
+def test_padded_3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    c = synth.coefficients(1300 + radius, 3, radius)
+    f = synth.grid_uniform(1400 + radius, tuple(n + 2 * radius for n in shape))
+    kmax = {1: 4, 2: 3, 3: 3, 4: 2}[radius]
+    tunes = []
+    for K in range(1, kmax + 1):
+        for nw, lz, wl in ((16, 5, 64), (16, 7, 32), (K * radius + 1, 3, 32)):
+            if nw <= 16 and nw * (64 // wl) > 2 * K * radius:
+                tunes.append((K, f"k={K},nw={nw},lz={lz},wl={wl}"))
+    tunes += [(1, "k=1,nw=16,lz=6,wl=32,pair=1"), (1, "k=1,rows=1,nbp=0,lz=4"),
+              (1, "k=1,rows=1,nbp=1,lz=64"), (1, "k=1,rows=2,nbp=0,lz=5"), (1, "naive")]
+    cache = {}
+    for K, tune in tunes:
+        steps = 2 * K + 1
+        if ("nbp=1" in tune or "rows=2" in tune) and f.shape[2] % 4:
+            continue
+        if steps not in cache:
+            cache[steps] = oracle_mod.star_run_padded(f, c, radius, steps, dtype=np.float32)
+        got, desc = run(torch, st, f, shape, radius, c, steps, boundary="padded", tune=tune)
+        assert_bitwise(got, cache[steps], f"padded 3D {shape} r{radius} [{desc}]")
+
+
+@pytest.mark.parametrize("radius", [5, 6, 7, 8])
+def test_padded_3d_high_radius_default(torch, st, oracle_mod, radius):
+    shape = (9, 12, 40)
+    c = synth.coefficients(1500 + radius, 3, radius)
+    f = synth.grid_uniform(1600 + radius, tuple(n + 2 * radius for n in shape))
+    got, desc = run(torch, st, f, shape, radius, c, 3, boundary="padded")
+    assert_bitwise(got, oracle_mod.star_run_padded(f, c, radius, 3, dtype=np.float32),
+                   f"padded 3D r{radius} [{desc}]")
+
+
+def test_padded_default_config_vs_fp64(torch, st, oracle_mod):
+    """Autoselected configurations, 30 steps, against the FP64 padded form."""
+    for shape, radius in (((130, 517), 3), ((40, 45, 130), 2)):
+        ndim = len(shape)
+        c = synth.coefficients(1700 + radius, ndim, radius)
+        f = synth.grid_uniform(1701, tuple(n + 2 * radius for n in shape))
+        got, desc = run(torch, st, f, shape, radius, c, 30, boundary="padded")
+        assert_bitwise(got, oracle_mod.star_run_padded(f, c, radius, 30, dtype=np.float32), desc)
+        ref = oracle_mod.star_run_padded(f, c, radius, 30)
+        assert oracle_mod.rel_linf(got, ref) <= TOL_F64, desc
+
+
+def sym_coeffs(seed, ndim, radius):
+    """Positive shared coefficients whose expansion sums to 1 (FP32)."""
+    w = 1.0 + synth.uniform01_f64(seed, 1 + ndim * radius)
+    return (w / (w[0] + 2.0 * w[1:].sum())).astype(np.float32)
+
+
+S2D = [(1, 1), (3, 5), (17, 33), (37, 513), (97, 1000), (64, 2048)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", S2D)
+def test_symmetric_2d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    c = sym_coeffs(1800 + radius, 2, radius)
+    f = synth.grid_uniform(1900 + radius, shape)
+    cache = {}
+    for K in (1, 2, 3, 4):
+        for ly in (7, 64):
+            steps = 2 * K + 1
+            if steps not in cache:
+                cache[steps] = oracle_mod.star_run_sym_f32(f, c, radius, steps)
+            got, desc = run(torch, st, f, shape, radius, c, steps, symmetric=True,
+                            tune=f"k={K},ly={ly}")
+            assert "coeffs=shared" in desc
+            assert_bitwise(got, cache[steps], f"shared 2D {shape} r{radius} [{desc}]")
+    got, desc = run(torch, st, f, shape, radius, c, 3, symmetric=True, tune="naive")
+    assert_bitwise(got, oracle_mod.star_run_sym_f32(f, c, radius, 3), "shared 2D naive")
+
+
+S3D = [(1, 1, 1), (3, 2, 5), (9, 17, 33), (20, 37, 300), (6, 3, 257), (11, 9, 512)]
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", S3D)
+def test_symmetric_3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
+    c = sym_coeffs(2100 + radius, 3, radius)
+    f = synth.grid_uniform(2200 + radius, shape)
+    want = oracle_mod.star_run_sym_f32(f, c, radius, 3)
+    tunes = [None, "k=1,rows=1,nbp=0,lz=4", "k=1,rows=1,nbp=0,lz=64", "naive"]
+    if shape[2] % 4 == 0:
+        tunes.append("k=1,rows=1,nbp=1,lz=5")
+    for tune in tunes:
+        got, desc = run(torch, st, f, shape, radius, c, 3, symmetric=True, tune=tune)
+        assert_bitwise(got, want, f"shared 3D {shape} r{radius} [{desc}]")
+
+
+def test_symmetric_default_vs_fp64(torch, st, oracle_mod):
+    for shape, radius in (((257, 1531), 4), ((40, 45, 130), 3)):
+        ndim = len(shape)
+        c = sym_coeffs(2300 + radius, ndim, radius)
+        f = synth.grid_uniform(2301, shape)
+        got, desc = run(torch, st, f, shape, radius, c, 40, symmetric=True)
+        assert_bitwise(got, oracle_mod.star_run_sym_f32(f, c, radius, 40), desc)
+        ref = oracle_mod.star_run_f64(f, oracle_mod.expand_symmetric(c, ndim, radius), radius, 40)
+        assert oracle_mod.rel_linf(got, ref) <= TOL_F64, desc
+
+
+def test_padded_and_shared_plans_in_a_batch(torch, st, oracle_mod):
+    """A batch hands padded and shared-coefficient grids to their own plans:
+    each output equals its own stencil_run, bit for bit."""
+    specs = [((30, 70), 2, dict(boundary="padded")), ((50, 260), 3, dict(symmetric=True)),
+             ((12, 16, 40), 1, dict(boundary="padded")), ((9, 10, 33), 2, dict(symmetric=True)),
+             ((40, 90), 4, {})]
+    plans, ins, outs, wants = [], [], [], []
+    for i, (shape, radius, kw) in enumerate(specs):
+        ndim = len(shape)
+        c = sym_coeffs(2400 + i, ndim, radius) if kw.get("symmetric") else \
+            synth.coefficients(2400 + i, ndim, radius)
+        p = st.Plan(shape, radius, c, **kw)
+        x = torch.from_numpy(synth.grid_uniform(2500 + i, p.array_shape)).cuda()
+        plans.append(p)
+        ins.append(x)
+        outs.append(torch.empty_like(x))
+        w = torch.empty_like(x)
+        p.run(x, w, 7)
+        wants.append(w)
+    st.run_batched(plans, ins, outs, 7)
+    torch.cuda.synchronize()
+    for o, w, (shape, radius, kw) in zip(outs, wants, specs):
+        assert torch.equal(o, w), (shape, radius, kw)
+    for p in plans:
+        p.close()

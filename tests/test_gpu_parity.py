@@ -380,6 +380,28 @@ def test_scaled_state_form_matches_model_bitwise(torch, st, radius, shape):
             plan.close()
 
 
+@pytest.mark.parametrize("radius", [1, 4])
+def test_precision_forms_multi_segment_bitwise(torch, st, radius):
+    """z-segments of 64 and 128 planes over 200 planes: tile maxima published
+    by several segments of one storage tile column, and the exponents staged
+    per segment, against the models of both forms."""
+    from oracle import precision
+    shape = (200, 40, 72)
+    c = synth.coefficients(1600 + radius, 3, radius)
+    f = synth.sinusoid_grid(1700 + radius, 200, modes=4)[:, :40, :72].copy()
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    for storage, codec, model in (("f16", precision.F16, precision.run),
+                                  ("bf16-scaled", precision.BF16, precision.run_scaled)):
+        want = model(f, c, radius, 6, 3, codec)
+        for tune in ("wl=32,nw=16,lz=64", "wl=32,nw=16,lz=128", "wl=64,nw=16,lz=64"):
+            plan = st.Plan(shape, radius, c, storage=storage, anchor_m=3, tune=tune)
+            plan.run(x, y, 6)
+            torch.cuda.synchronize()
+            assert_bitwise(y.cpu().numpy(), want, f"{storage} {tune} r{radius} [{plan.describe()}]")
+            plan.close()
+
+
 def test_precision_form_error_and_speed_report(torch, st, oracle_mod):
     """Small sinusoid field: FP16/BF16 error against FP64 stays in the model's range."""
     shape = (64, 64, 128)

@@ -126,3 +126,47 @@ def test_scaled_state_error_against_fp64(oracle_mod, codec, tol):
     # accurate than re-rounding the whole state
     d1 = oracle_mod.rel_linf(precision.run(f, c, radius, steps, 1, codec), ref)
     assert d1 < errs[0] / 5, (d1, errs[0])
+
+
+def adversarial_fields():
+    """Fields that stress the per-tile scales: a single-tile spike beside
+    near-zero tiles, sign flips cell by cell, and a step between tiles."""
+    shape = (70, 66, 130)  # three tiles along x, two along y and z (ragged)
+    spike = np.full(shape, 1e-6, dtype=np.float32)
+    spike[5:9, 60:66, 62:66] = 1000.0          # at a tile corner, next to small tiles
+    flips = np.where((np.indices(shape).sum(axis=0) % 2) == 0, 1.0, -1.0).astype(np.float32)
+    flips *= synth.grid_uniform(41, shape) + np.float32(0.5)
+    step = np.zeros(shape, dtype=np.float32)
+    step[:, :, 64:] = np.float32(3.0e4)
+    return {"spike": spike, "flips": flips, "step": step}
+
+
+@pytest.mark.parametrize("codec", [precision.F16, precision.BF16])
+@pytest.mark.parametrize("form", ["delta", "scaled"])
+def test_codes_stay_within_the_headroom(codec, form):
+    """Every value handed to the encoder, scaled by its tile's 2^-e, stays
+    within 2^14 (1 + 2^-11): the exponent rule leaves a binade below FP16's
+    largest finite value, whatever the field (not a property of one
+    schedule: it must hold for any field and step count)."""
+    limit = 2.0 ** 14 * (1.0 + 2.0 ** -11)
+    c = synth.coefficients(42, 3, 2)
+    for name, f in adversarial_fields().items():
+        seen = []
+        obs = lambda kind, scaled: seen.append(float(np.max(np.abs(scaled))))
+        if form == "delta":
+            out = precision.run(f, c, 2, 7, 4, codec, observe=obs)
+        else:
+            out = precision.run_scaled(f, c, 2, 7, 4, codec, observe=obs)
+        assert seen and max(seen) <= limit, (name, max(seen))
+        assert np.all(np.isfinite(out)), name
+
+
+def test_delta_error_grows_with_the_anchor_interval():
+    """Against the FP64 definition, the anchored delta's error grows with m
+    (more steps accumulate in the low-precision delta between anchors)."""
+    f = synth.sinusoid_grid(4, 40)
+    c = synth.coefficients(43, 3, 3)
+    ref = oracle.star_run_f64(f, c, 3, 60)
+    errs = [oracle.rel_linf(precision.run(f, c, 3, 60, m, precision.F16), ref) for m in (1, 4, 15, 60)]
+    assert errs[0] <= errs[1] <= errs[2] <= errs[3], errs
+    assert errs[3] > 4 * errs[1], errs
