@@ -35,7 +35,28 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", "-fvisibility=hidden", "-I", INCLUDE, "-
           "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=off", "-fno-gpu-rdc",
           # no packed FP32 (v_pk_*_f32) instructions: plain VALU FP32 only
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # per-kernel register and scratch use, recorded next to each object
+          "-Rpass-analysis=kernel-resource-usage"]
+RESOURCE_FIELDS = ("VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]")
+
+
+def _record_resources(obj: str, stderr: str):
+    """Writes <obj>.resources: one line per kernel, its mangled name then
+    VGPRs, AGPRs, scratch bytes per lane and occupancy (waves per SIMD), from
+    the compiler's kernel-resource-usage remarks."""
+    rows, cur = [], None
+    for line in stderr.splitlines():
+        if "Function Name: " in line:
+            cur = {"name": line.split("Function Name: ", 1)[1].strip()}
+            rows.append(cur)
+        elif cur is not None:
+            for f in RESOURCE_FIELDS:
+                if f + ": " in line:
+                    cur[f] = (line.split(f + ": ", 1)[1].split() or ["?"])[0]
+    with open(obj + ".resources", "w") as fh:
+        for r in rows:
+            fh.write(" ".join([r["name"]] + [r.get(f, "?") for f in RESOURCE_FIELDS]) + "\n")
 
 
 def _hipcc() -> str:
@@ -103,8 +124,13 @@ def build(verbose: bool = False, asm_dir: str | None = None, jobs: int | None = 
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode == 0 and "-Rpass-analysis=kernel-resource-usage" in cmd:
+            _record_resources(cmd[cmd.index("-o") + 1], r.stderr)
         err = "\n".join(l for l in r.stderr.splitlines()
-                        if "packed-fp32-ops" not in l and l.strip())
+                        if "packed-fp32-ops" not in l and l.strip() and "remark:" not in l
+                        and not l.lstrip().startswith(("Function Name", "VGPRs", "AGPRs",
+                                                       "ScratchSize", "Dynamic Stack",
+                                                       "Occupancy", "SGPRs", "LDS Size")))
         if r.returncode != 0:
             raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{err}")
         if err and verbose:

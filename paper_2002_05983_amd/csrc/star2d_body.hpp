@@ -213,17 +213,16 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
                     // the fixed frame of the padded array keeps its values:
                     // a frame cell takes its centre (this stage's input)
                     const bool frame_row = r < pad || r >= ny - pad;
-                    auto keep_frame = [&](const float (&ctr)[VEC]) STAR_INLINE {
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            const int c = col0 + e;
-                            res[e] = (frame_row || c < pad || c >= nx - pad) ? ctr[e] : res[e];
-                        }
-                    };
-                    if constexpr (S == 1)
-                        keep_frame(q0[(PH - R + NQ) % NQ]);
-                    else
-                        keep_frame(q[S - 2][(PH % P - R + P) % P]);
+                    for (int e = 0; e < VEC; ++e) {
+                        float ctr;
+                        if constexpr (S == 1)
+                            ctr = q0[(PH - R + NQ) % NQ][e];
+                        else
+                            ctr = q[S - 2][(PH % P - R + P) % P][e];
+                        const int c = col0 + e;
+                        res[e] = (frame_row || c < pad || c >= nx - pad) ? ctr : res[e];
+                    }
                 }
             }
             if constexpr (S < K) {

@@ -264,19 +264,12 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             load_plane(zstart + decltype(phc)::value, q0[decltype(phc)::value]);
     });
 
-    // Padded-halo frame: a frame cell of plane r keeps its centre value ctr.
+    // Padded-halo frame: a frame cell (element e of this lane's row, plane
+    // r) keeps its centre value ctr; other cells keep v.
     const bool frame_row = y < pad || y >= ny - pad;
-    auto keep_frame = [&](int r, const float (&ctr)[VEC], float (&res)[VEC]) STAR_INLINE {
-        if constexpr (EDGE) {
-            if (pad > 0) {
-                const bool frame = frame_row || r < pad || r >= nz - pad;
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    const int c = col0 + e;
-                    res[e] = (frame || c < pad || c >= nx - pad) ? ctr[e] : res[e];
-                }
-            }
-        }
+    auto frame_value = [&](int r, int e, float ctr, float v) STAR_INLINE -> float {
+        const int c = col0 + e;
+        return (frame_row || r < pad || r >= nz - pad || c < pad || c >= nx - pad) ? ctr : v;
     };
 
     // The output row of plane r (stage K), masked to the tile and grid.
@@ -338,15 +331,25 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
                 if (n < 2 * S * R || !computes(S)) return;
                 const int r = zl - S * R;  // plane produced by stage S
                 float res[VEC];
-                if constexpr (S == 1) {
+                if constexpr (S == 1)
                     cells(std::integral_constant<int, NQ>{},
                           std::integral_constant<int, (PH - R + NQ) % NQ>{}, q0, 0, b, res);
-                    keep_frame(r, q0[(PH - R + NQ) % NQ], res);
-                } else {
+                else
                     cells(std::integral_constant<int, P>{},
                           std::integral_constant<int, (PS - R + P) % P>{}, q[S - 2], S - 1, b,
                           res);
-                    keep_frame(r, q[S - 2][(PS - R + P) % P], res);
+                if constexpr (EDGE) {
+                    if (pad > 0) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            float ctr;
+                            if constexpr (S == 1)
+                                ctr = q0[(PH - R + NQ) % NQ][e];
+                            else
+                                ctr = q[S - 2][(PS - R + P) % P][e];
+                            res[e] = frame_value(r, e, ctr, res[e]);
+                        }
+                    }
                 }
                 if constexpr (S < K) {
                     constexpr int WS = PS;
@@ -398,7 +401,13 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             float res[VEC];
             cells(std::integral_constant<int, NQ>{}, std::integral_constant<int, (PH0 - R + NQ) % NQ>{},
                   q0, 0, b, res);
-            keep_frame(zl - R, q0[(PH0 - R + NQ) % NQ], res);
+            if constexpr (EDGE) {
+                if (pad > 0) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        res[e] = frame_value(zl - R, e, q0[(PH0 - R + NQ) % NQ][e], res[e]);
+                }
+            }
             store_row(zl - R, res);
         }
         // one plane at a time: interleaving the two would raise the
@@ -408,7 +417,13 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             float res[VEC];
             cells(std::integral_constant<int, NQ>{}, std::integral_constant<int, (PH1 - R + NQ) % NQ>{},
                   q0, 0, b + 1, res);
-            keep_frame(zl + 1 - R, q0[(PH1 - R + NQ) % NQ], res);
+            if constexpr (EDGE) {
+                if (pad > 0) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        res[e] = frame_value(zl + 1 - R, e, q0[(PH1 - R + NQ) % NQ][e], res[e]);
+                }
+            }
             store_row(zl + 1 - R, res);
         }
     };

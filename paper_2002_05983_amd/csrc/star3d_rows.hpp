@@ -227,17 +227,12 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
         for (int e = 0; e < VEC; ++e) res[e] = acc[e];
     };
 
-    // Padded-halo frame: a frame cell of plane r, own row k keeps its centre.
-    auto keep_frame = [&](int r, int k, const float (&ctr)[VEC], float (&res)[VEC]) STAR_INLINE {
-        if (pad > 0) {
-            const int yy = rows0 + k;
-            const bool frame = r < pad || r >= nz - pad || yy < pad || yy >= ny - pad;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const int cc = col0 + e;
-                res[e] = (frame || cc < pad || cc >= nx - pad) ? ctr[e] : res[e];
-            }
-        }
+    // Padded-halo frame: a frame cell (element e of own row k, plane r)
+    // keeps its centre value ctr; other cells keep v.
+    auto frame_value = [&](int r, int k, int e, float ctr, float v) STAR_INLINE -> float {
+        const int yy = rows0 + k, cc = col0 + e;
+        return (r < pad || r >= nz - pad || yy < pad || yy >= ny - pad || cc < pad ||
+                cc >= nx - pad) ? ctr : v;
     };
 
     auto store_row = [&](int r, int k, const float (&res)[VEC]) STAR_INLINE {
@@ -283,7 +278,10 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
         for (int k = 0; k < RPL; ++k) {
             float res[VEC];
             cells(std::integral_constant<int, CS>{}, k, std::integral_constant<int, B>{}, res);
-            keep_frame(r, k, q[CS][k], res);
+            if (pad > 0) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) res[e] = frame_value(r, k, e, q[CS][k][e], res[e]);
+            }
             store_row(r, k, res);
         }
     };
