@@ -64,6 +64,62 @@ __device__ __forceinline__ float from_upper_lane_or_zero(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf,
                                                               0xf, true));
 }
+// Fused wave shift: a[k] += c * (v[k] of the lane below) for k < N (UP =
+// false), or of the lane above (UP = true): one v_fmac_f32 per value with
+// the wave shift on its first operand, in place of a v_mov_b32_dpp and a
+// v_fmac_f32 (the compiler fuses DPP moves into adds and multiplies but not
+// into FMAs).  The lane with no source reads 0.  Each result is the same
+// correctly rounded fma(c, v_shifted, a).  c must be in a VGPR (vgpr_copy).
+// The s_nop 1 gives the two wait states a DPP read needs after a VALU write
+// of its source register, which the compiler does not insert for inline
+// assembly; within the block no instruction writes a shifted source.
+#define STAR_FSH(dir, a, v, c) "v_fmac_f32_dpp %" #a ", %" #v ", %" #c " " dir \
+    " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+template <bool UP, int N>
+__device__ __forceinline__ void fma_shifted(float *a, float c, const float *v) {
+    static_assert(N >= 1 && N <= 4, "1..4 values per block");
+    if constexpr (N == 1) {
+        if constexpr (UP)
+            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 1, 2) : "+v"(a[0]) : "v"(v[0]), "v"(c));
+        else
+            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 1, 2) : "+v"(a[0]) : "v"(v[0]), "v"(c));
+    } else if constexpr (N == 2) {
+        if constexpr (UP)
+            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 2, 4) STAR_FSH("wave_shl:1", 1, 3, 4)
+                : "+v"(a[0]), "+v"(a[1]) : "v"(v[0]), "v"(v[1]), "v"(c));
+        else
+            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 2, 4) STAR_FSH("wave_shr:1", 1, 3, 4)
+                : "+v"(a[0]), "+v"(a[1]) : "v"(v[0]), "v"(v[1]), "v"(c));
+    } else if constexpr (N == 3) {
+        if constexpr (UP)
+            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 3, 6) STAR_FSH("wave_shl:1", 1, 4, 6)
+                    STAR_FSH("wave_shl:1", 2, 5, 6)
+                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]) : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(c));
+        else
+            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 3, 6) STAR_FSH("wave_shr:1", 1, 4, 6)
+                    STAR_FSH("wave_shr:1", 2, 5, 6)
+                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]) : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(c));
+    } else {
+        if constexpr (UP)
+            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 4, 8) STAR_FSH("wave_shl:1", 1, 5, 8)
+                    STAR_FSH("wave_shl:1", 2, 6, 8) STAR_FSH("wave_shl:1", 3, 7, 8)
+                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
+                : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(c));
+        else
+            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 4, 8) STAR_FSH("wave_shr:1", 1, 5, 8)
+                    STAR_FSH("wave_shr:1", 2, 6, 8) STAR_FSH("wave_shr:1", 3, 7, 8)
+                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
+                : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(c));
+    }
+}
+#undef STAR_FSH
+// A wave-uniform value copied into a VGPR (an operand that must be a VGPR).
+__device__ __forceinline__ float vgpr_copy(float s) {
+    float v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 // Value of v in lane `lane` (wave-uniform lane index), broadcast to all lanes.
 __device__ __forceinline__ float lane_value(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));

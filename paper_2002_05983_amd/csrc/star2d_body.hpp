@@ -16,7 +16,8 @@
 //     (y0-(K-s)*R) is due, 2*s*R rows into the stream.  Each stage keeps the last 2R+1 rows of its input
 //     in a register queue: the y-neighbours.  The x-neighbours of the
 //     queue's centre row come from the lane's own registers and, across the
-//     lane boundary, from the adjacent lanes through DPP wave shifts.  Only
+//     lane boundary, from the adjacent lanes through DPP wave shifts (fused
+//     into the FMA that uses them in the interior form, R <= 4).  Only
 //     the K-th stage is written back, so one pass moves 8 bytes per cell for
 //     K steps.
 //   * Halo cells are recomputed by neighbouring strips instead of exchanged
@@ -47,10 +48,65 @@ constexpr int VEC = kVec2D;
 // SYM: shared coefficients, one per axis and distance (cf holds c_C, then
 // c_x,i, c_y,i for i = 1..R): per distance, one FMA with the rounded sum of
 // the W and E cells, then one with the sum of the S and N cells.
+// W and E coefficients of distances 1..R held in VGPRs, for the FMAs that
+// take their operand from the adjacent lane (fused-shift form).
+template <int R>
+struct XCoefV {
+    float w[R + 1], e[R + 1];
+};
+
+// Fused-shift form: the interior form with per-point coefficients and
+// R <= 4, where each x-neighbour across the lane boundary comes from the
+// adjacent lane and the lanes at the wavefront's ends hold halo columns
+// (their values never reach the output): such an FMA takes the neighbour
+// through the wave shift of its own operand (fma_shifted), which saves the
+// separate shift of each of the 2R border values of a row.
+template <int R, bool EDGE, bool SYM>
+constexpr bool star2d_fused_shift() { return !EDGE && !SYM && R <= VEC; }
+
 template <int R, int NS, int CS, bool EDGE, bool SYM = false>
 __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
-                                           float (&res)[VEC]) {
+                                           const XCoefV<R> &xv, float (&res)[VEC]) {
     static_assert(R <= 2 * VEC, "x-neighbours come from the lanes at most two away");
+    if constexpr (star2d_fused_shift<R, EDGE, SYM>()) {
+        // distance by distance over the lane's cells: each cell's FMAs keep
+        // their order (W, E, S, N per distance); the FMAs of one distance
+        // and side that reach across the lane boundary form one fused block
+        float acc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = cf.c[0] * q[CS][e];
+        static_for<1, R + 1>([&](auto ic) STAR_INLINE {
+            constexpr int i = decltype(ic)::value;
+            // W: cells e >= i read their own lane, cells e < i the lane below
+#pragma unroll
+            for (int e = i; e < VEC; ++e)
+                acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], q[CS][e - i], acc[e]);
+            {
+                float v[i];
+#pragma unroll
+                for (int e = 0; e < i; ++e) v[e] = q[CS][VEC + e - i];
+                fma_shifted<false, i>(acc, xv.w[i], v);
+            }
+            // E: the first VEC - i cells read their own lane, the last i the lane above
+#pragma unroll
+            for (int e = 0; e < VEC - i; ++e)
+                acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], q[CS][e + i], acc[e]);
+            {
+                float v[i];
+#pragma unroll
+                for (int e = 0; e < i; ++e) v[e] = q[CS][e];
+                fma_shifted<true, i>(acc + (VEC - i), xv.e[i], v);
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], q[(CS - i + NS) % NS][e], acc[e]);
+                acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kN, i)], q[(CS + i) % NS][e], acc[e]);
+            }
+        });
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) res[e] = acc[e];
+        return;
+    }
     auto lower = [&](float v) STAR_INLINE {
         return EDGE ? from_lower_lane(v, q[CS][0]) : from_lower_lane_or_zero(v);
     };
@@ -168,6 +224,15 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
         }
     };
 
+    XCoefV<R> xv;
+    if constexpr (star2d_fused_shift<R, EDGE, SYM>()) {
+#pragma unroll
+        for (int i = 1; i <= R; ++i) {
+            xv.w[i] = vgpr_copy(cf.c[coef_index<2>(kW, i)]);
+            xv.e[i] = vgpr_copy(cf.c[coef_index<2>(kE, i)]);
+        }
+    }
+
     // q0: ring of NQ input rows, loaded straight into their slots.
     // q[s-1] (s = 2..K): last P rows of the stage-(s-1) field.
     float q0[NQ][VEC];
@@ -205,9 +270,9 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
             const int r = j - S * R;  // row produced by stage S
             float res[VEC];
             if constexpr (S == 1)
-                star2d_row<R, NQ, (PH - R + NQ) % NQ, EDGE, SYM>(q0, cf, res);
+                star2d_row<R, NQ, (PH - R + NQ) % NQ, EDGE, SYM>(q0, cf, xv, res);
             else
-                star2d_row<R, P, (PH % P - R + P) % P, EDGE, SYM>(q[S - 2], cf, res);
+                star2d_row<R, P, (PH % P - R + P) % P, EDGE, SYM>(q[S - 2], cf, xv, res);
             if constexpr (EDGE) {
                 if (pad > 0) {
                     // the fixed frame of the padded array keeps its values:
