@@ -335,7 +335,7 @@ def bench_forms(stencil, synth, torch, dev, side2=SIDE, side3=512, time_steps2=2
     for ndim, side, steps in ((2, side2, time_steps2), (3, side3, time_steps3)):
         shape = (side,) * ndim
         for r in RADII:
-            tune = f"k={min(4, 16 // r)},ly=256" if ndim == 2 else "k=1,rows=1,nbp=1,lz=128"
+            tune = f"k={min(4, 16 // r)},ly=64" if ndim == 2 else "k=1,rows=1,nbp=1,lz=128"
             c = synth.coefficients(4000 + 10 * ndim + r, ndim, r)
             w = 1.0 + synth.uniform01_f64(4100 + 10 * ndim + r, 1 + ndim * r)
             sym = (w / (w[0] + 2.0 * w[1:].sum())).astype(np.float32)

@@ -113,6 +113,13 @@ __device__ __forceinline__ void fma_shifted(float *a, float c, const float *v) {
     }
 }
 #undef STAR_FSH
+// W and E coefficients of distances 1..R held in VGPRs, for the FMAs that
+// take their operand from the adjacent lane through fma_shifted.
+template <int R>
+struct XCoefV {
+    float w[R + 1], e[R + 1];
+};
+
 // A wave-uniform value copied into a VGPR (an operand that must be a VGPR).
 __device__ __forceinline__ float vgpr_copy(float s) {
     float v;

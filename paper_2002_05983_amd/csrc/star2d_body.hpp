@@ -48,13 +48,6 @@ constexpr int VEC = kVec2D;
 // SYM: shared coefficients, one per axis and distance (cf holds c_C, then
 // c_x,i, c_y,i for i = 1..R): per distance, one FMA with the rounded sum of
 // the W and E cells, then one with the sum of the S and N cells.
-// W and E coefficients of distances 1..R held in VGPRs, for the FMAs that
-// take their operand from the adjacent lane (fused-shift form).
-template <int R>
-struct XCoefV {
-    float w[R + 1], e[R + 1];
-};
-
 // Fused-shift form: the interior form with per-point coefficients and
 // R <= 4, where each x-neighbour across the lane boundary comes from the
 // adjacent lane and the lanes at the wavefront's ends hold halo columns
@@ -181,6 +174,8 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
     const int jlast = jstart + niter - 1;
     const bool left_edge = xs < 0;
     const bool right_edge = xs + 64 * VEC > nx;
+    // the wavefront holds a column of the padded-halo frame
+    const bool frame_cols = xs < pad || xs + 64 * VEC > nx - pad;
     const int out_lo = max(xs + H, 0);
     const int out_hi = min(xs + H + TX, nx);
 
@@ -274,10 +269,12 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
             else
                 star2d_row<R, P, (PH % P - R + P) % P, EDGE, SYM>(q[S - 2], cf, xv, res);
             if constexpr (EDGE) {
-                if (pad > 0) {
-                    // the fixed frame of the padded array keeps its values:
-                    // a frame cell takes its centre (this stage's input)
-                    const bool frame_row = r < pad || r >= ny - pad;
+                // the fixed frame of the padded array keeps its values: a
+                // frame cell takes its centre (this stage's input); the
+                // per-cell select only where the row or the wavefront's
+                // columns touch the frame (wave-uniform test)
+                const bool frame_row = r < pad || r >= ny - pad;
+                if (pad > 0 && (frame_row || frame_cols)) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         float ctr;
