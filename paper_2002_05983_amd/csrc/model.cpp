@@ -13,7 +13,8 @@
 //           than SIMDs;
 // plus a launch cost.  Instruction counts are written from the kernels'
 // structure (4 cells per lane, one FMA per point, 2R lane shifts per row and
-// stage) with a per-row overhead constant; the constants are fitted to this
+// stage, fused into the FMAs of the 2D interior form for R <= 4) with a
+// per-row overhead constant; the constants are fitted to this
 // GPU's measurements and the fit is reported as model accuracy.
 #include <algorithm>
 #include <cmath>
@@ -58,7 +59,8 @@ Pass model_2d(const stencil_plan_s *p, int K) {
     // stage s starts 2sR rows into the stream: sum over s of (rows - 2sR)
     const double stage_rows = K * (ly + (K - 1.0) * R);
     const double waves = nstrips * nsegs;
-    const double per_stage_row = kVec2D * (4.0 * R + 1.0) + 2.0 * R + kRowStage2D;
+    // lane shifts: 2R per row, fused into the FMAs for R <= 4 (interior form)
+    const double per_stage_row = kVec2D * (4.0 * R + 1.0) + (R <= 4 ? 0.0 : 2.0 * R) + kRowStage2D;
     const double per_wave = rows * kRow2D + stage_rows * per_stage_row;
     const double instr = waves * per_wave;
     Pass s;
@@ -133,7 +135,13 @@ Pass model_3r(const stencil_plan_s *p) {
     s.t_valu = waves * lz * p->s3_rpl * per_row * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
     s.t_plane = 0.0;
     const double cells = nx * ny * nz;
-    s.t_hbm = (cells * 4.0 * (lz + 2.0 * R) / lz + cells * 4.0) / kHbmEff3D;
+    // the 2R neighbour rows of each centre plane come from L2 when the
+    // neighbouring wavefronts loaded them moments before; the fraction that
+    // misses grows with R (FETCH_SIZE on 512^3: 2.2-3.1x the algorithmic
+    // reads at R = 3, 4; near 1x at R = 1)
+    const double miss = std::min(0.3, 0.1 * (R - 1));
+    const double reads = (lz + 2.0 * R) / lz * (1.0 + 2.0 * R * miss / p->s3_rpl);
+    s.t_hbm = (cells * 4.0 * reads + cells * 4.0) / kHbmEff3D;
     return s;
 }
 
