@@ -147,14 +147,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 __device__ __forceinline__ int masked_offset(int off, bool ok) {
     return (int)((unsigned)off | ((unsigned)(!ok) << 31));
 }
+// Cache-policy bits of a store (gfx950): 2 marks it non-temporal, for
+// outputs a pass never reads again, so that they do not push rows other
+// wavefronts are about to read out of L2.
+constexpr int kStoreNT = 2;
+template <int AUX = 0>
 __device__ __forceinline__ void buffer_store4(__amdgpu_buffer_rsrc_t r, int off, float a, float b,
                                               float c, float d) {
     const v4i v = {__builtin_bit_cast(int, a), __builtin_bit_cast(int, b),
                    __builtin_bit_cast(int, c), __builtin_bit_cast(int, d)};
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void buffer_store1(__amdgpu_buffer_rsrc_t r, int off, float a) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, a), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, a), r, off, 0, AUX);
 }
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by block id.

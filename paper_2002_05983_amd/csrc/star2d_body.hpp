@@ -316,13 +316,13 @@ __device__ __forceinline__ void star2d_body(const float *__restrict__ src, float
                 const auto rs = buffer_rsrc(dst + (size_t)clampi(r, ny) * (size_t)nx, nx * 4);
                 if constexpr (ALIGNED) {
                     const bool ok = row_ok && col0 >= out_lo && col0 + VEC <= out_hi;
-                    buffer_store4(rs, ok ? col0 * 4 : kOutOfRange, res[0], res[1], res[2], res[3]);
+                    buffer_store4<kStoreNT>(rs, ok ? col0 * 4 : kOutOfRange, res[0], res[1], res[2], res[3]);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const int c = col0 + e;
                         const bool ok = row_ok && c >= out_lo && c < out_hi;
-                        buffer_store1(rs, ok ? c * 4 : kOutOfRange, res[e]);
+                        buffer_store1<kStoreNT>(rs, ok ? c * 4 : kOutOfRange, res[e]);
                     }
                 }
             }
@@ -354,12 +354,16 @@ __device__ __forceinline__ bool star2d_interior(int nx, int ny, int ly, int stri
 }
 
 // Rows in flight per wavefront: two y-windows for the memory-bound small-K
-// passes, one otherwise, and 8 rows (8 KiB per wavefront) for single-step
-// passes of R >= 5, where a whole window would cost more registers than the
-// latency needs.  With K > 1 it must be a multiple of the window (the
-// stages' window slots are derived from the input-ring slot).
+// passes and for R = 1, K = 8 (measured on 16384^2: +2 %; at K = 5..7 the
+// extra registers cost a wave per SIMD and 2-4 %), one otherwise, and 8
+// rows (8 KiB per wavefront) for single-step passes of R >= 5, where a
+// whole window would cost more registers than the latency needs.  With
+// K > 1 it must be a multiple of the window (the stages' window slots are
+// derived from the input-ring slot).
 template <int R, int K>
-constexpr int prefetch_rows() { return K * R <= 2 ? 2 * (2 * R + 1) : (K == 1 && R >= 5) ? 8 : 2 * R + 1; }
+constexpr int prefetch_rows() {
+    return (K * R <= 2 || (R == 1 && K == 8)) ? 2 * (2 * R + 1) : (K == 1 && R >= 5) ? 8 : 2 * R + 1;
+}
 
 }  // namespace s2d
 }  // namespace star

@@ -284,7 +284,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             for (int c = 0; c < VEC / 4; ++c) {
                 const int cc = col0 + 4 * c;
                 const bool ok = ok_row && cc >= out_lo && cc + 4 <= out_hi;
-                buffer_store4(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[4 * c], res[4 * c + 1],
+                buffer_store4<kStoreNT>(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[4 * c], res[4 * c + 1],
                               res[4 * c + 2], res[4 * c + 3]);
             }
         } else {
@@ -292,7 +292,7 @@ __device__ __forceinline__ void star3d_body(const float *__restrict__ src, float
             for (int e = 0; e < VEC; ++e) {
                 const int cc = col0 + e;
                 const bool ok = ok_row && cc >= out_lo && cc < out_hi;
-                buffer_store1(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[e]);
+                buffer_store1<kStoreNT>(rs, ok ? (rowoff + cc) * 4 : kOutOfRange, res[e]);
             }
         }
     };

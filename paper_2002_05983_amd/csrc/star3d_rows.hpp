@@ -242,12 +242,15 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
         const int rowoff = clampi(yy, ny) * nx;
         if constexpr (ALIGNED) {
             const bool ok = ok_row && col0 < nx;
-            buffer_store4(rs, ok ? (rowoff + col0) * 4 : kOutOfRange, res[0], res[1], res[2], res[3]);
+            // non-temporal: keeps L2 for the neighbour rows (measured on
+            // 512^3: +4..7 % at R = 1, 3, 6, 8)
+            buffer_store4<kStoreNT>(rs, ok ? (rowoff + col0) * 4 : kOutOfRange, res[0], res[1],
+                                    res[2], res[3]);
         } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const bool ok = ok_row && col0 + e < nx;
-                buffer_store1(rs, ok ? (rowoff + col0 + e) * 4 : kOutOfRange, res[e]);
+                buffer_store1<kStoreNT>(rs, ok ? (rowoff + col0 + e) * 4 : kOutOfRange, res[e]);
             }
         }
     };
