@@ -5,12 +5,12 @@
 // here: a pass of K fused steps is bounded by the largest of
 //   HBM     bytes the pass must move / effective bandwidth;
 //   VALU    wavefront instructions / (CUs x SIMDs), 4 cycles per wave64
-//           instruction on a 16-lane SIMD;
-//   stream  the sequential path: (3D) the per-plane critical path of a
+//           instruction on a 16-lane SIMD; in 2D counted in rounds of the
+//           wavefronts each SIMD holds (estimated from the kernel's
+//           registers), a SIMD with a lone wavefront issuing at half rate;
+//   stream  (3D) the sequential path: the per-plane critical path of a
 //           workgroup -- its VALU issue, LDS write, barrier, LDS reads --
-//           times the planes each CU streams one after the other; (2D) the
-//           rows a wavefront streams alone when there are fewer wavefronts
-//           than SIMDs;
+//           times the planes each CU streams one after the other;
 // plus a launch cost.  Instruction counts are written from the kernels'
 // structure (4 cells per lane, one FMA per point, 2R lane shifts per row and
 // stage, fused into the FMAs of the 2D interior form for R <= 4) with a
@@ -31,23 +31,63 @@ constexpr double kCUs = 256.0;
 constexpr double kSimdPerCU = 4.0;
 constexpr double kClock = 2.4e9;             // Hz
 constexpr double kCyclesPerWaveInstr = 4.0;  // wave64 on a 16-lane SIMD
-// Fitted to the autotuner's measurements on MI355X (every candidate of 13
-// problems: 2D 16384^2 and 4096^2, 3D 512^3, 768^3 and 192x256x320) by a
-// grid search minimising mean |log(predicted / measured)|:
+// Fitted to the autotuner's measurements on MI355X (every candidate of 23
+// problems: 2D 16384^2 at R = 1..8 and 4096^2 at R = 1..4, 3D 512^3 at
+// R = 1..8, 768^3, 256^3 and 192x256x320) by a coordinate grid search
+// minimising the median |log(predicted / measured)| plus the shortfall of
+// the model's pick from the measured best:
 constexpr double kHbmEff2D = 5.0e12, kHbmEff3D = 5.0e12;  // B/s reached by the passes
 // s per pass: launch, plus (2D) the ramp-up and drain of the last wavefronts
-constexpr double kLaunch2D = 30e-6, kLaunch3D = 2e-6;
+constexpr double kLaunch2D = 30e-6, kLaunch3D = 10e-6;
 // instructions per wavefront row and stage beyond the FMAs and lane shifts
-// (clamps, register moves, index arithmetic), and per streamed row
-constexpr double kRowStage2D = 10.0, kRow2D = 16.0;
-constexpr double kRowStage3D = 25.0, kRow3D = 24.0, kLoadOnly3D = 20.0;
+// (clamps, register moves, index arithmetic, issue stalls), and per streamed row
+constexpr double kRowStage2D = 10.0, kRow2D = 6.0;
+constexpr double kRowStage3D = 25.0, kRow3D = 24.0, kLoadOnly3D = 30.0;
+// a wavefront alone on its SIMD issues one VALU instruction per kLoneIssue x
+// 4 cycles (dependent FMA chains); kLoneIssue of them keep the SIMD busy
+constexpr double kLoneIssue = 2.0;
 // per-plane critical path of a 3D workgroup beyond its VALU issue time
 // (LDS write, barrier, LDS reads), cycles
-constexpr double kPlaneLatency3D = 400.0;
+constexpr double kPlaneLatency3D = 300.0;
+// the xy-tile kernel spills above radius 4 (its z-queue of 2R+1 planes
+// outgrows 128 VGPRs): issue time x (1 + kSpill (KR - 4)^2), and fused
+// steps from radius 4 on x (1 + kSpillK (K - 1) R)
+constexpr double kSpill = 0.5, kSpillK = 0.1;
+// the row layout's neighbour rows that miss L2: kMissSlope (R - 1), at most kMissMax
+constexpr double kMissSlope = 0.1, kMissMax = 0.2;
 
 struct Pass {
     double t_hbm, t_valu, t_plane;
 };
+
+// Rows in flight per 2D wavefront (the rule of prefetch_rows in
+// star2d_body.hpp) and the resulting waves per SIMD: 4 floats per row of
+// the input ring and of the K-1 stage windows, ~24 registers besides.
+int prefetch_2d(int R, int K) {
+    if (K * R <= 2 || (R == 1 && K == 8)) return 2 * (2 * R + 1);
+    if (K == 1 && R >= 5) return 8;
+    return 2 * R + 1;
+}
+int waves_per_simd_2d(int R, int K) {
+    const int P = 2 * R + 1;
+    const int vgprs = (kVec2D * (P + prefetch_2d(R, K) + (K - 1) * P) + 24 + 7) / 8 * 8;
+    return std::max(1, std::min(8, 512 / vgprs));
+}
+
+// Issue time of `waves` wavefronts of `per_wave` VALU instructions on the
+// 1024 SIMDs, at most `occ` at a time on each: full rounds, then the rest
+// spread evenly; a SIMD holding w < kLoneIssue wavefronts issues w
+// instructions per kLoneIssue x 4 cycles.
+double simd_time(double waves, double per_wave, int occ) {
+    const double simds = kCUs * kSimdPerCU, slots = simds * occ;
+    const double full = std::floor(waves / slots), rest = waves - full * slots;
+    double t = full * occ * per_wave * std::max(1.0, kLoneIssue / occ);
+    if (rest > 0) {
+        const double w = std::ceil(rest / simds);
+        t += w * per_wave * std::max(1.0, kLoneIssue / w);
+    }
+    return t * kCyclesPerWaveInstr / kClock;
+}
 
 Pass model_2d(const stencil_plan_s *p, int K) {
     const int R = p->radius;
@@ -62,11 +102,9 @@ Pass model_2d(const stencil_plan_s *p, int K) {
     // lane shifts: 2R per row, fused into the FMAs for R <= 4 (interior form)
     const double per_stage_row = kVec2D * (4.0 * R + 1.0) + (R <= 4 ? 0.0 : 2.0 * R) + kRowStage2D;
     const double per_wave = rows * kRow2D + stage_rows * per_stage_row;
-    const double instr = waves * per_wave;
     Pass s;
-    s.t_valu = instr * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
-    // few wavefronts: each streams its rows alone on its SIMD
-    s.t_plane = std::ceil(waves / (kCUs * kSimdPerCU)) * per_wave * kCyclesPerWaveInstr / kClock;
+    s.t_valu = simd_time(waves, per_wave, waves_per_simd_2d(R, K));
+    s.t_plane = 0.0;
     // wind-up rows are re-read from HBM; the overlapped halo columns of
     // neighbouring strips mostly come from L2
     const double cells = nx * ny;
@@ -101,13 +139,16 @@ Pass model_3d(const stencil_plan_s *p, int K) {
     const double per_stage_plane = vec * (6.0 * R + 1.0) + 2.0 * R + kRowStage3D;
     const double instr_block = planes * (compute * kRow3D + load_only * kLoadOnly3D) +
                                stage_planes * compute * per_stage_plane;
+    double spill = 1.0;
+    if (R >= 5 && K * R > 4) spill += kSpill * (K * R - 4.0) * (K * R - 4.0);
+    if (R >= 4 && K > 1) spill += kSpillK * (K - 1.0) * R;
     Pass s;
-    s.t_valu = blocks * instr_block * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
+    s.t_valu = blocks * instr_block * spill * kCyclesPerWaveInstr / (kCUs * kSimdPerCU * kClock);
     // one workgroup per CU at a time (1024 threads, <= 128 VGPRs): the
     // plane loop of each CU's blocks runs back to back, each plane its
     // SIMD's share of the issue plus the barrier/LDS latency
     const double waves_per_simd = std::ceil(nw / kSimdPerCU);
-    const double issue_cycles = waves_per_simd * (instr_block / nw) * kCyclesPerWaveInstr;
+    const double issue_cycles = waves_per_simd * (instr_block / nw) * spill * kCyclesPerWaveInstr;
     const double rounds = std::ceil(blocks / kCUs);
     // one barrier and LDS round trip per plane, per pair of planes when paired
     const double barriers = p->s3_pair ? std::ceil(planes / 2.0) : planes;
@@ -139,7 +180,7 @@ Pass model_3r(const stencil_plan_s *p) {
     // neighbouring wavefronts loaded them moments before; the fraction that
     // misses grows with R (FETCH_SIZE on 512^3: 2.2-3.1x the algorithmic
     // reads at R = 3, 4; near 1x at R = 1)
-    const double miss = std::min(0.3, 0.1 * (R - 1));
+    const double miss = std::min(kMissMax, kMissSlope * (R - 1));
     const double reads = (lz + 2.0 * R) / lz * (1.0 + 2.0 * R * miss / p->s3_rpl);
     s.t_hbm = (cells * 4.0 * reads + cells * 4.0) / kHbmEff3D;
     return s;

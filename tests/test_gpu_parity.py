@@ -459,7 +459,8 @@ def test_precision_workload_128cube_vs_stored_fp64(torch, st, storage, m, tol):
 def test_model_predictions_and_errors(torch, st):
     p2 = st.Plan((4096, 4096), 2, synth.coefficients(3, 2, 2))
     m = p2.model()
-    assert m["GCell/s"] > 0 and m["hbm_us"] > 0 and m["valu_us"] > 0 and m["plane_us"] > 0
+    # 2D: no sequential-path term (a lone wavefront's slower issue is in the VALU time)
+    assert m["GCell/s"] > 0 and m["hbm_us"] > 0 and m["valu_us"] > 0 and m["plane_us"] == 0
     # more fused steps move fewer bytes per step: higher predicted rate, HBM time per pass unchanged
     assert p2.model("k=4,ly=128")["GCell/s"] > p2.model("k=1,ly=128")["GCell/s"]
     with pytest.raises(ValueError):
