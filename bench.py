@@ -102,7 +102,7 @@ def flop_per_cell(ndim: int, radius: int) -> int:
     return 8 * radius + 1 if ndim == 2 else 12 * radius + 1
 
 
-def cpu_baseline(f0, coeffs_by_r, sample_steps: int = 20):
+def cpu_baseline(f0, coeffs_by_r, sample_steps: int = 40):
     """The FP64 oracle, unchanged, timed on the host: sample_steps steps per
     radius on the full grid."""
     from oracle import oracle
