@@ -298,11 +298,14 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
     });
 }
 
-// Planes in flight per wavefront: enough to cover the memory latency while
-// the ring plus the neighbour rows stay within 128 VGPRs.
+// Planes in flight per wavefront: enough to cover the memory latency at
+// R <= 2; from R = 3 on one plane, which shortens the time between a
+// wavefront loading its own row and its neighbours reading that row back
+// from L2 (512^3, R = 3, two rows per wavefront: 530 -> 547 GCell/s; equal
+// elsewhere).
 template <int R, int RPL>
 constexpr int prefetch_rows3() {
-    return RPL == 1 ? (R <= 2 ? 6 : R <= 4 ? 3 : 2) : (R <= 2 ? 3 : 2);
+    return R <= 2 ? (RPL == 1 ? 6 : 3) : 1;
 }
 
 }  // namespace s3r
