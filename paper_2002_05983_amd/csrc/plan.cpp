@@ -234,12 +234,12 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             if (p->s3_rpl == 0) p->s3_rpl = 1;
             if (p->K != 1 || p->storage != STENCIL_F32 || p->s3_pair)
                 return star_set_error(STENCIL_EINVAL, "rows= is a single-step FP32 layout (k=1, no pair)");
-            if (p->s3_rpl > 2 || (p->s3_rpl == 2 && R > 4))
-                return star_set_error(STENCIL_EINVAL, "rows must be 1, or 2 for R <= 4");
+            if (p->s3_rpl == 3 || p->s3_rpl > 4 || (p->s3_rpl > 1 && R > 4) || (p->s3_rpl == 4 && p->s3_nbp))
+                return star_set_error(STENCIL_EINVAL, "rows must be 1, or 2 or 4 for R <= 4 (4 without nbp)");
             if (p->sym && p->s3_rpl != 1)
                 return star_set_error(STENCIL_EINVAL, "shared coefficients run one row per wavefront");
-            if ((p->s3_rpl == 2 || p->s3_nbp) && p->nx % 4 != 0)
-                return star_set_error(STENCIL_EINVAL, "rows=2 and nbp=1 need rows of 16 bytes (nx % 4 == 0)");
+            if ((p->s3_rpl > 1 || p->s3_nbp) && p->nx % 4 != 0)
+                return star_set_error(STENCIL_EINVAL, "rows=2, 4 and nbp=1 need rows of 16 bytes (nx % 4 == 0)");
             if (p->s3_lz == 0) p->s3_lz = default_lz_rows(p);
             if (p->s3_lz < 1) return star_set_error(STENCIL_EINVAL, "lz must be >= 1");
             p->vec = 4;

@@ -86,6 +86,8 @@ hipError_t STAR_CAT(launch_star3d_rows_r, STAR_R)(const Star3DArgs &a, hipStream
     if constexpr (STAR_R <= 4) {
         if (a.rows == 2)
             return a.nbp ? launch_rows<2, true, true>(a, stream) : launch_rows<2, false, true>(a, stream);
+        // four rows per wavefront: 2R neighbour rows per 4 output rows
+        if (a.rows == 4 && !a.nbp) return launch_rows<4, false, true>(a, stream);
     }
     return hipErrorInvalidValue;
 }

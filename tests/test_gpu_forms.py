@@ -100,11 +100,12 @@ def test_padded_3d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
             if nw <= 16 and nw * (64 // wl) > 2 * K * radius:
                 tunes.append((K, f"k={K},nw={nw},lz={lz},wl={wl}"))
     tunes += [(1, "k=1,nw=16,lz=6,wl=32,pair=1"), (1, "k=1,rows=1,nbp=0,lz=4"),
-              (1, "k=1,rows=1,nbp=1,lz=64"), (1, "k=1,rows=2,nbp=0,lz=5"), (1, "naive")]
+              (1, "k=1,rows=1,nbp=1,lz=64"), (1, "k=1,rows=2,nbp=0,lz=5"),
+              (1, "k=1,rows=4,nbp=0,lz=7"), (1, "naive")]
     cache = {}
     for K, tune in tunes:
         steps = 2 * K + 1
-        if ("nbp=1" in tune or "rows=2" in tune) and f.shape[2] % 4:
+        if ("nbp=1" in tune or "rows=2" in tune or "rows=4" in tune) and f.shape[2] % 4:
             continue
         if steps not in cache:
             cache[steps] = oracle_mod.star_run_padded(f, c, radius, steps, dtype=np.float32)
