@@ -41,7 +41,12 @@ constexpr double kHbmEff2D = 5.0e12, kHbmEff3D = 5.0e12;  // B/s reached by the 
 constexpr double kLaunch2D = 30e-6, kLaunch3D = 10e-6;
 // instructions per wavefront row and stage beyond the FMAs and lane shifts
 // (clamps, register moves, index arithmetic, issue stalls), and per streamed row
-constexpr double kRowStage2D = 10.0, kRow2D = 6.0;
+constexpr double kRowStage2D = 5.0, kRow2D = 2.0;
+// Measured in 2D, not derived: the rate falls with the segment length at
+// high K (16384^2, R = 1, K = 8: 4263 GCell/s at ly = 64, 2987 at ly = 384;
+// flat at K = 1), fitted as a factor 1 + kLyPenalty (ly/64 - 1) K/8 on the
+// pass time.
+constexpr double kLyPenalty = 0.1;
 constexpr double kRowStage3D = 25.0, kRow3D = 24.0, kLoadOnly3D = 30.0;
 // a wavefront alone on its SIMD issues one VALU instruction per kLoneIssue x
 // 4 cycles (dependent FMA chains); kLoneIssue of them keep the SIMD busy
@@ -58,6 +63,7 @@ constexpr double kMissSlope = 0.1, kMissMax = 0.2;
 
 struct Pass {
     double t_hbm, t_valu, t_plane;
+    double scale = 1.0;  // empirical factor on the pass time
 };
 
 // Rows in flight per 2D wavefront (the rule of prefetch_rows in
@@ -105,6 +111,7 @@ Pass model_2d(const stencil_plan_s *p, int K) {
     Pass s;
     s.t_valu = simd_time(waves, per_wave, waves_per_simd_2d(R, K));
     s.t_plane = 0.0;
+    s.scale = 1.0 + kLyPenalty * std::max(0.0, ly / 64.0 - 1.0) * K / 8.0;
     // wind-up rows are re-read from HBM; the overlapped halo columns of
     // neighbouring strips mostly come from L2
     const double cells = nx * ny;
@@ -202,7 +209,7 @@ extern "C" int stencil_plan_model(stencil_plan_t plan, const char *config, doubl
                    : trial.s3_rpl > 0 ? model_3r(&trial)
                                       : model_3d(&trial, trial.K);
     const double t =
-        std::max({s.t_hbm, s.t_valu, s.t_plane}) + (trial.ndim == 2 ? kLaunch2D : kLaunch3D);
+        (std::max({s.t_hbm, s.t_valu, s.t_plane}) + (trial.ndim == 2 ? kLaunch2D : kLaunch3D)) * s.scale;
     out[0] = (double)trial.ncells * trial.K / t / 1e9;
     out[1] = s.t_hbm * 1e6;
     out[2] = s.t_valu * 1e6;
