@@ -17,7 +17,7 @@
 //     in a register queue: the y-neighbours.  The x-neighbours of the
 //     queue's centre row come from the lane's own registers and, across the
 //     lane boundary, from the adjacent lanes through DPP wave shifts (fused
-//     into the FMA that uses them in the interior form, R <= 4).  Only
+//     into the FMA that uses them in the interior form).  Only
 //     the K-th stage is written back, so one pass moves 8 bytes per cell for
 //     K steps.
 //   * Halo cells are recomputed by neighbouring strips instead of exchanged
@@ -48,14 +48,15 @@ constexpr int VEC = kVec2D;
 // SYM: shared coefficients, one per axis and distance (cf holds c_C, then
 // c_x,i, c_y,i for i = 1..R): per distance, one FMA with the rounded sum of
 // the W and E cells, then one with the sum of the S and N cells.
-// Fused-shift form: the interior form with per-point coefficients and
-// R <= 4, where each x-neighbour across the lane boundary comes from the
-// adjacent lane and the lanes at the wavefront's ends hold halo columns
-// (their values never reach the output): such an FMA takes the neighbour
-// through the wave shift of its own operand (fma_shifted), which saves the
-// separate shift of each of the 2R border values of a row.
+// Fused-shift form: the interior form with per-point coefficients, where
+// the lanes at the wavefront's ends hold halo columns (their values never
+// reach the output): an FMA whose x-neighbour lies in the adjacent lane
+// takes it through the wave shift of its own operand (fma_shifted), which
+// saves the separate shift of each of the 2R border values of a row; a
+// neighbour two lanes away (distances 5..8) moves one lane by a plain
+// shift first.
 template <int R, bool EDGE, bool SYM>
-constexpr bool star2d_fused_shift() { return !EDGE && !SYM && R <= VEC; }
+constexpr bool star2d_fused_shift() { return !EDGE && !SYM && R <= 2 * VEC; }
 
 template <int R, int NS, int CS, bool EDGE, bool SYM = false>
 __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coefs &cf,
@@ -70,25 +71,37 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
         for (int e = 0; e < VEC; ++e) acc[e] = cf.c[0] * q[CS][e];
         static_for<1, R + 1>([&](auto ic) STAR_INLINE {
             constexpr int i = decltype(ic)::value;
-            // W: cells e >= i read their own lane, cells e < i the lane below
+            // cells whose neighbour at distance i lies in another lane: the
+            // first (W) or last (E) NX of them; at i > VEC two lanes away for
+            // some, whose value first moves one lane by a plain shift
+            constexpr int NX = i < VEC ? i : VEC;
+            // W: cells e >= i read their own lane, cells e < i the lanes below
 #pragma unroll
             for (int e = i; e < VEC; ++e)
                 acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], q[CS][e - i], acc[e]);
             {
-                float v[i];
+                float v[NX];
 #pragma unroll
-                for (int e = 0; e < i; ++e) v[e] = q[CS][VEC + e - i];
-                fma_shifted<false, i>(acc, xv.w[i], v);
+                for (int e = 0; e < NX; ++e) {
+                    const int off = e - i;  // column offset from the lane's base, < 0
+                    v[e] = (off >= -VEC) ? q[CS][(VEC + off) & (VEC - 1)]
+                                         : from_lower_lane_or_zero(q[CS][(2 * VEC + off) & (VEC - 1)]);
+                }
+                fma_shifted<false, NX>(acc, xv.w[i], v);
             }
-            // E: the first VEC - i cells read their own lane, the last i the lane above
+            // E: the first VEC - i cells read their own lane, the rest the lanes above
 #pragma unroll
             for (int e = 0; e < VEC - i; ++e)
                 acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], q[CS][e + i], acc[e]);
             {
-                float v[i];
+                float v[NX];
 #pragma unroll
-                for (int e = 0; e < i; ++e) v[e] = q[CS][e];
-                fma_shifted<true, i>(acc + (VEC - i), xv.e[i], v);
+                for (int k = 0; k < NX; ++k) {
+                    const int off = VEC - NX + k + i - VEC;  // element in the lane above, >= 0
+                    v[k] = (off < VEC) ? q[CS][off & (VEC - 1)]
+                                       : from_upper_lane_or_zero(q[CS][(off - VEC) & (VEC - 1)]);
+                }
+                fma_shifted<true, NX>(acc + (VEC - NX), xv.e[i], v);
             }
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
