@@ -64,52 +64,49 @@ __device__ __forceinline__ float from_upper_lane_or_zero(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf,
                                                               0xf, true));
 }
-// Fused wave shift: a[k] += c * (v[k] of the lane below) for k < N (UP =
-// false), or of the lane above (UP = true): one v_fmac_f32 per value with
-// the wave shift on its first operand, in place of a v_mov_b32_dpp and a
-// v_fmac_f32 (the compiler fuses DPP moves into adds and multiplies but not
-// into FMAs).  The lane with no source reads 0.  Each result is the same
-// correctly rounded fma(c, v_shifted, a).  c must be in a VGPR (vgpr_copy).
-// The s_nop 1 gives the two wait states a DPP read needs after a VALU write
-// of its source register, which the compiler does not insert for inline
-// assembly; within the block no instruction writes a shifted source.
+// Fused wave shift: a += c * (v of the lane below / above) as one
+// v_fmac_f32 with the wave shift on its first operand, in place of a
+// v_mov_b32_dpp and a v_fmac_f32 (the compiler fuses DPP moves into adds
+// and multiplies but not into FMAs).  The lane with no source reads 0.
+// Each result is the same correctly rounded fma(c, v_shifted, a).  c must
+// be in a VGPR (vgpr_copy).  The s_nop 1 gives the two wait states a DPP
+// read needs after a VALU write of its source register, which the compiler
+// does not insert for inline assembly; within a block no instruction
+// writes a shifted source.
 #define STAR_FSH(dir, a, v, c) "v_fmac_f32_dpp %" #a ", %" #v ", %" #c " " dir \
     " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-template <bool UP, int N>
-__device__ __forceinline__ void fma_shifted(float *a, float c, const float *v) {
-    static_assert(N >= 1 && N <= 4, "1..4 values per block");
-    if constexpr (N == 1) {
-        if constexpr (UP)
-            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 1, 2) : "+v"(a[0]) : "v"(v[0]), "v"(c));
-        else
-            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 1, 2) : "+v"(a[0]) : "v"(v[0]), "v"(c));
-    } else if constexpr (N == 2) {
-        if constexpr (UP)
-            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 2, 4) STAR_FSH("wave_shl:1", 1, 3, 4)
-                : "+v"(a[0]), "+v"(a[1]) : "v"(v[0]), "v"(v[1]), "v"(c));
-        else
-            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 2, 4) STAR_FSH("wave_shr:1", 1, 3, 4)
-                : "+v"(a[0]), "+v"(a[1]) : "v"(v[0]), "v"(v[1]), "v"(c));
-    } else if constexpr (N == 3) {
-        if constexpr (UP)
-            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 3, 6) STAR_FSH("wave_shl:1", 1, 4, 6)
-                    STAR_FSH("wave_shl:1", 2, 5, 6)
-                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]) : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(c));
-        else
-            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 3, 6) STAR_FSH("wave_shr:1", 1, 4, 6)
-                    STAR_FSH("wave_shr:1", 2, 5, 6)
-                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]) : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(c));
+// Both sides of one distance I in one block (4 cells per lane): a[e] +=
+// cw * (vw[e] of the lane below) for the first min(I, 4) cells, then
+// a[e] += ce * (ve[k] of the lane above) for the last min(I, 4) cells
+// (k = e - (4 - min(I, 4))): every cell still takes its W term before its
+// E term, and the block needs the wait states once.
+template <int I>
+__device__ __forceinline__ void fma_shifted_we(float (&a)[4], float cw, const float *vw, float ce,
+                                               const float *ve) {
+    static_assert(I >= 1, "distance >= 1");
+    if constexpr (I == 1) {
+        asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 2, 4) STAR_FSH("wave_shl:1", 1, 3, 5)
+            : "+v"(a[0]), "+v"(a[3]) : "v"(vw[0]), "v"(ve[0]), "v"(cw), "v"(ce));
+    } else if constexpr (I == 2) {
+        asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 4, 8) STAR_FSH("wave_shr:1", 1, 5, 8)
+                STAR_FSH("wave_shl:1", 2, 6, 9) STAR_FSH("wave_shl:1", 3, 7, 9)
+            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
+            : "v"(vw[0]), "v"(vw[1]), "v"(ve[0]), "v"(ve[1]), "v"(cw), "v"(ce));
+    } else if constexpr (I == 3) {
+        asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 4, 10) STAR_FSH("wave_shr:1", 1, 5, 10)
+                STAR_FSH("wave_shr:1", 2, 6, 10) STAR_FSH("wave_shl:1", 1, 7, 11)
+                STAR_FSH("wave_shl:1", 2, 8, 11) STAR_FSH("wave_shl:1", 3, 9, 11)
+            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
+            : "v"(vw[0]), "v"(vw[1]), "v"(vw[2]), "v"(ve[0]), "v"(ve[1]), "v"(ve[2]), "v"(cw),
+              "v"(ce));
     } else {
-        if constexpr (UP)
-            asm("s_nop 1\n\t" STAR_FSH("wave_shl:1", 0, 4, 8) STAR_FSH("wave_shl:1", 1, 5, 8)
-                    STAR_FSH("wave_shl:1", 2, 6, 8) STAR_FSH("wave_shl:1", 3, 7, 8)
-                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
-                : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(c));
-        else
-            asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 4, 8) STAR_FSH("wave_shr:1", 1, 5, 8)
-                    STAR_FSH("wave_shr:1", 2, 6, 8) STAR_FSH("wave_shr:1", 3, 7, 8)
-                : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
-                : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(c));
+        asm("s_nop 1\n\t" STAR_FSH("wave_shr:1", 0, 4, 12) STAR_FSH("wave_shr:1", 1, 5, 12)
+                STAR_FSH("wave_shr:1", 2, 6, 12) STAR_FSH("wave_shr:1", 3, 7, 12)
+                STAR_FSH("wave_shl:1", 0, 8, 13) STAR_FSH("wave_shl:1", 1, 9, 13)
+                STAR_FSH("wave_shl:1", 2, 10, 13) STAR_FSH("wave_shl:1", 3, 11, 13)
+            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3])
+            : "v"(vw[0]), "v"(vw[1]), "v"(vw[2]), "v"(vw[3]), "v"(ve[0]), "v"(ve[1]), "v"(ve[2]),
+              "v"(ve[3]), "v"(cw), "v"(ce));
     }
 }
 #undef STAR_FSH

@@ -75,34 +75,32 @@ __device__ __forceinline__ void star2d_row(const float (&q)[NS][VEC], const Coef
             // first (W) or last (E) NX of them; at i > VEC two lanes away for
             // some, whose value first moves one lane by a plain shift
             constexpr int NX = i < VEC ? i : VEC;
-            // W: cells e >= i read their own lane, cells e < i the lanes below
+            // W terms of the cells e >= i (own lane), then one fused block
+            // with the W terms of the first NX cells (lanes below) and the
+            // E terms of the last NX (lanes above), then the E terms of the
+            // cells e < VEC - i (own lane): each cell keeps W before E
 #pragma unroll
             for (int e = i; e < VEC; ++e)
                 acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kW, i)], q[CS][e - i], acc[e]);
             {
-                float v[NX];
+                float vw[NX], ve[NX];
 #pragma unroll
                 for (int e = 0; e < NX; ++e) {
                     const int off = e - i;  // column offset from the lane's base, < 0
-                    v[e] = (off >= -VEC) ? q[CS][(VEC + off) & (VEC - 1)]
-                                         : from_lower_lane_or_zero(q[CS][(2 * VEC + off) & (VEC - 1)]);
+                    vw[e] = (off >= -VEC) ? q[CS][(VEC + off) & (VEC - 1)]
+                                          : from_lower_lane_or_zero(q[CS][(2 * VEC + off) & (VEC - 1)]);
                 }
-                fma_shifted<false, NX>(acc, xv.w[i], v);
+#pragma unroll
+                for (int k = 0; k < NX; ++k) {
+                    const int off = k + i - NX;  // element in the lane above, >= 0
+                    ve[k] = (off < VEC) ? q[CS][off & (VEC - 1)]
+                                        : from_upper_lane_or_zero(q[CS][(off - VEC) & (VEC - 1)]);
+                }
+                fma_shifted_we<i>(acc, xv.w[i], vw, xv.e[i], ve);
             }
-            // E: the first VEC - i cells read their own lane, the rest the lanes above
 #pragma unroll
             for (int e = 0; e < VEC - i; ++e)
                 acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kE, i)], q[CS][e + i], acc[e]);
-            {
-                float v[NX];
-#pragma unroll
-                for (int k = 0; k < NX; ++k) {
-                    const int off = VEC - NX + k + i - VEC;  // element in the lane above, >= 0
-                    v[k] = (off < VEC) ? q[CS][off & (VEC - 1)]
-                                       : from_upper_lane_or_zero(q[CS][(off - VEC) & (VEC - 1)]);
-                }
-                fma_shifted<true, NX>(acc + (VEC - NX), xv.e[i], v);
-            }
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 acc[e] = __builtin_fmaf(cf.c[coef_index<2>(kS, i)], q[(CS - i + NS) % NS][e], acc[e]);
