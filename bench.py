@@ -238,8 +238,8 @@ def bench_single_step(stencil, synth, torch, dev, side2=SIDE, side3=512, time_st
         if ndim == 2:
             cands = [f"k=1,ly={ly}" for ly in (64, 128, 256)]
         else:
-            cands = [f"k=1,wl={wl},vec={v},nw=16,lz={lz}" for wl, v in ((32, 4), (64, 4), (64, 8))
-                     for lz in (64, 128, 256)]
+            cands = [f"k=1,wl={wl},vec={v},nw={nw},lz={lz}" for wl, v in ((32, 4), (64, 4), (64, 8))
+                     for nw in (12, 16) for lz in (64, 128, 256)]
             cands += [f"k=1,rows={rows},nbp={nbp},lz={lz}" for rows in (1, 2, 4) for nbp in (0, 1)
                       for lz in (32, 64, 128) if not (rows == 4 and nbp)]
         for r in RADII:
