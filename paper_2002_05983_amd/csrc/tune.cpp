@@ -188,10 +188,12 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float
             }
         }
     }
-    for (const std::string &cand : cands) {
+    // GCell/s of one configuration over a run of about `target_ms`
+    // (after a warm-up), or a negative value when it cannot run.
+    auto time_config = [&](const std::string &cand, float target_ms) -> double {
         stencil_plan_s trial = saved;
         trial.scratch = saved.scratch;
-        if (plan_configure(&trial, cand.c_str()) != STENCIL_OK) continue;
+        if (plan_configure(&trial, cand.c_str()) != STENCIL_OK) return -1.0;
         const int K = trial.K;
         auto time_run = [&](int64_t n, float *ms) {
             return hipEventRecord(e0, st) == hipSuccess &&
@@ -199,21 +201,35 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const float *in, float
                    hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                    hipEventElapsedTime(ms, e0, e1) == hipSuccess && *ms > 0.0f;
         };
-        // warm-up, then a run scaled to last a few milliseconds
         int64_t steps = 4 * K;
         float ms = 0.0f;
         if (plan_enqueue(&trial, in, out, 2 * K, st) != hipSuccess || !time_run(steps, &ms)) {
             (void)hipGetLastError();
-            continue;
+            return -1.0;
         }
-        if (ms < 2.0f) {
-            steps = std::max<int64_t>(K, (int64_t)(steps * 4.0f / std::max(ms, 0.01f)) / K * K);
+        if (ms < target_ms / 2) {
+            steps = std::max<int64_t>(K, (int64_t)(steps * target_ms / std::max(ms, 0.01f)) / K * K);
             if (!time_run(steps, &ms)) {
                 (void)hipGetLastError();
-                continue;
+                return -1.0;
             }
         }
-        results.push_back({cand, (double)plan->ncells * (double)steps / (ms * 1e-3) / 1e9});
+        return (double)plan->ncells * (double)steps / (ms * 1e-3) / 1e9;
+    };
+    for (const std::string &cand : cands) {
+        const double g = time_config(cand, 4.0f);
+        if (g > 0.0) results.push_back({cand, g});
+    }
+    // The first sweep times each candidate once over a few milliseconds;
+    // the leaders often lie within that run's noise of each other, so the
+    // best three are timed again over longer runs (best of two) before one
+    // is picked.
+    std::stable_sort(results.begin(), results.end(),
+                     [](const Result &a, const Result &b) { return a.gcells > b.gcells; });
+    for (size_t i = 0; i < results.size() && i < 3; ++i) {
+        double g = -1.0;
+        for (int rep = 0; rep < 2; ++rep) g = std::max(g, time_config(results[i].config, 16.0f));
+        if (g > 0.0) results[i].gcells = g;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
