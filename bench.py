@@ -577,8 +577,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
-              file=sys.stderr)
+              "(a grid would shard along its slowest axis with K*R ghost rows per face "
+              "and pass); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
