@@ -53,7 +53,7 @@ enum stencil_status {
     STENCIL_EINVAL = -1,       /* bad argument (nothing was enqueued)        */
     STENCIL_ENOMEM = -2,       /* device or host allocation failed           */
     STENCIL_EDEVICE = -3,      /* a HIP call or kernel launch failed         */
-    STENCIL_EUNSUPPORTED = -4, /* valid request this build does not support  */
+    STENCIL_EUNSUPPORTED = -4, /* valid request the library does not support */
     STENCIL_EOVERFLOW = -5     /* a low-precision tile scale left its range  */
 };
 

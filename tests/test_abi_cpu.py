@@ -91,7 +91,7 @@ def test_plan_rejects_invalid_arguments(lib, case):
 def test_plan_radius_limits(lib):
     """Radius 1..8 in 2D and 3D.  In 3D, K is at most 2 at radius 5, 6
     and 1 at radius 7, 8 (a larger k is invalid), and low-precision storage
-    is a valid request this build does not support above radius 4.  Decided
+    is a valid request the library does not support above radius 4.  Decided
     before any device call."""
     for ndim in (2, 3):
         rc, h = _plan(lib, ndim, [4] * ndim, 9, [0.0] * (1 + 2 * ndim * 9))
