@@ -17,13 +17,15 @@ namespace {
 // Resident wavefronts the 2D kernel aims for: 256 CUs x 4 SIMDs x 4.
 constexpr int64_t kTargetWaves2D = 4096;
 
-// Defaults measured on a 16384^2 grid (temporal degree and segment rows).
+// Defaults measured on a 16384^2 grid (temporal degree and segment rows):
+// the autotuner's picks there.
 int default_k2d(int R) {
     switch (R) {
         case 1: return 8;
-        case 2: return 5;
+        case 2: return 6;
         case 3: return 4;
-        case 4: return 4;
+        case 4: return 3;
+        case 5: return 3;
         default: return max_k2d(R);
     }
 }
@@ -31,7 +33,9 @@ int default_k2d(int R) {
 int default_ly(const stencil_plan_s *p, int K) {
     const int tx = star2d_tile_x(K, p->radius);
     const int64_t nstrips = (p->nx + tx - 1) / tx;
-    int64_t ly = (p->radius == 4 && K == 4) ? 256 : 128;
+    // short segments: more wavefronts for the tail of the launch, at the
+    // price of re-read wind-up rows (measured best at 64..96 rows)
+    int64_t ly = p->radius >= 5 ? 96 : 64;
     // small grids: keep enough wavefronts to fill the chip
     const int64_t want = (p->ny * nstrips + kTargetWaves2D - 1) / kTargetWaves2D;
     ly = std::min<int64_t>(ly, std::max<int64_t>(want, 8 * K * p->radius));
@@ -111,7 +115,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
     } else {
         // defaults measured on a 512^3 grid
         p->variant = STAR_S3D;
-        p->K = (p->storage != STENCIL_F32) ? 1 : R == 1 ? 4 : R == 2 ? 2 : 1;
+        p->K = (p->storage != STENCIL_F32) ? 1 : R == 1 ? 3 : R == 2 ? 2 : 1;
         p->vec = 0;   // chosen below from the grid width
         p->s3_rows = 16;
         p->s3_lanes = 32;
@@ -128,6 +132,13 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         if (R >= 6 && p->storage == STENCIL_F32) {
             p->s3_rpl = 1;
             p->s3_nbp = p->nx % 4 == 0 ? 1 : 0;
+        }
+        // At R = 3, 4 the row layout with four rows per wavefront (16-byte
+        // rows) beats the tile kernel's single step (512^3: 561 and 528
+        // against 522 and 516 GCell/s)
+        if ((R == 3 || R == 4) && p->storage == STENCIL_F32 && p->nx % 4 == 0) {
+            p->s3_rpl = 4;
+            p->s3_nbp = 0;
         }
         // shared coefficients are built into the row layout only
         if (p->sym) {
