@@ -123,15 +123,16 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->s3_pair = 0;
         p->s3_rpl = 0;
         p->s3_nbp = 0;
-        // Above radius 5 the xy-tile kernel's z-queue of 2R+1 planes no
+        // Above radius 4 the xy-tile kernel's z-queue of 2R+1 planes no
         // longer fits a 1024-thread workgroup's 128 VGPRs (it spills) and 2R
         // of its 32 tile rows are halo; the LDS-free row layout keeps every
-        // cell an output cell and runs without spills: measured on 512^3 it
-        // is 1.35x, 3.3x and 5.3x the best other single-step form at
-        // R = 6, 7, 8 (the xy-tile kernel stays ahead at R <= 5)
-        if (R >= 6 && p->storage == STENCIL_F32) {
-            p->s3_rpl = 1;
-            p->s3_nbp = p->nx % 4 == 0 ? 1 : 0;
+        // cell an output cell.
+        // From radius 5 on the row layout leads (512^3, two rows per
+        // wavefront: 386, 346, 317, 283 GCell/s at R = 5..8 against at most
+        // 358, 201, 76, 45 for the tile kernel); unaligned rows take one row
+        if (R >= 5 && p->storage == STENCIL_F32) {
+            p->s3_rpl = p->nx % 4 == 0 ? 2 : 1;
+            p->s3_nbp = 0;
         }
         // At R = 3, 4 the row layout with four rows per wavefront (16-byte
         // rows) beats the tile kernel's single step (512^3: 561 and 528
@@ -245,8 +246,10 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             if (p->s3_rpl == 0) p->s3_rpl = 1;
             if (p->K != 1 || p->storage != STENCIL_F32 || p->s3_pair)
                 return star_set_error(STENCIL_EINVAL, "rows= is a single-step FP32 layout (k=1, no pair)");
-            if (p->s3_rpl == 3 || p->s3_rpl > 4 || (p->s3_rpl > 1 && R > 4) || (p->s3_rpl == 4 && p->s3_nbp))
-                return star_set_error(STENCIL_EINVAL, "rows must be 1, or 2 or 4 for R <= 4 (4 without nbp)");
+            if (p->s3_rpl == 3 || p->s3_rpl > 4 || (p->s3_rpl == 4 && (R > 4 || p->s3_nbp)) ||
+                (p->s3_rpl == 2 && R > 4 && p->s3_nbp))
+                return star_set_error(STENCIL_EINVAL,
+                                      "rows must be 1, 2 (nbp=0 above R = 4) or 4 (R <= 4, nbp=0)");
             if (p->sym && p->s3_rpl != 1)
                 return star_set_error(STENCIL_EINVAL, "shared coefficients run one row per wavefront");
             if ((p->s3_rpl > 1 || p->s3_nbp) && p->nx % 4 != 0)

@@ -83,9 +83,13 @@ hipError_t STAR_CAT(launch_star3d_rows_r, STAR_R)(const Star3DArgs &a, hipStream
         return launch_rows<1, false, false>(a, stream);
     }
     if (a.rows == 1) return a.nbp ? launch_rows<1, true, true>(a, stream) : launch_rows<1, false, true>(a, stream);
-    if constexpr (STAR_R <= 4) {
-        if (a.rows == 2)
+    if (a.rows == 2) {
+        if constexpr (STAR_R <= 4)
             return a.nbp ? launch_rows<2, true, true>(a, stream) : launch_rows<2, false, true>(a, stream);
+        else  // two rows per wavefront above radius 4: no neighbour prefetch (registers)
+            return a.nbp ? hipErrorInvalidValue : launch_rows<2, false, true>(a, stream);
+    }
+    if constexpr (STAR_R <= 4) {
         // four rows per wavefront: 2R neighbour rows per 4 output rows
         if (a.rows == 4 && !a.nbp) return launch_rows<4, false, true>(a, stream);
     }

@@ -68,8 +68,9 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
             // prefetch, segment length
             for (int rows : {1, 2, 4})
                 for (int nbp : {0, 1}) {
-                    if (rows > 1 && (R > 4 || p->sym)) continue;
-                    if (rows == 4 && nbp) continue;
+                    if (rows > 1 && p->sym) continue;
+                    if (rows == 4 && (nbp || R > 4)) continue;
+                    if (rows == 2 && R > 4 && nbp) continue;
                     if ((rows > 1 || nbp) && p->nx % 4 != 0) continue;
                     for (int lz : {32, 64, 128, 256}) {
                         if (lz > p->nz && lz != 32) continue;

@@ -165,7 +165,8 @@ def test_batch_entry_points_reject_null(lib):
     (3, [64, 64, 64], 1, b"wl=16", False),
     (3, [64, 64, 64], 4, b"k=1,rows=2,nbp=1,lz=32", True),
     (3, [64, 64, 64], 5, b"k=1,rows=1,nbp=0", True),
-    (3, [64, 64, 64], 5, b"k=1,rows=2", False),          # two rows per wavefront up to R = 4
+    (3, [64, 64, 64], 5, b"k=1,rows=2", True),           # two rows per wavefront above R = 4 ...
+    (3, [64, 64, 64], 6, b"k=1,rows=2,nbp=1", False),    # ... without neighbour prefetch
     (3, [64, 64, 64], 4, b"k=1,rows=4,nbp=0", True),     # four rows, no neighbour prefetch
     (3, [64, 64, 64], 4, b"k=1,rows=4,nbp=1", False),
     (3, [64, 64, 64], 5, b"k=1,rows=4", False),
