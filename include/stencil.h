@@ -163,11 +163,15 @@ STENCIL_API int stencil_coeffs_per_direction(int ndim, int radius, const float *
  *            workgroup, <= 16), "lz=" (planes per segment) and "pair=1" (two
  *            planes per barrier, k=1, vec=4) for the xy-tile kernel; or the
  *            LDS-free single-step row layout: "rows=" (grid rows per
- *            wavefront, 1, or 2 for R <= 4), "nbp=" (0/1: neighbour rows
- *            loaded one plane ahead; rows=2 and nbp=1 need nx % 4 == 0) and
- *            "lz=".  E.g. "k=4,ly=256" (2D), "k=2,wl=32,nw=16,lz=64",
- *            "k=1,rows=1,nbp=1,lz=128" (3D).  Unknown keys or infeasible
- *            values give EINVAL.
+ *            wavefront: 1; 2; 4 for R <= 4), "nbp=" (0/1: neighbour rows
+ *            loaded one plane ahead, R <= 4 with rows=1, 2), "lpr=" (lanes
+ *            per grid row: 64, the default, or 16 -- four rows of a
+ *            64-column strip per wavefront, for narrow grids; rows=1,
+ *            nbp=0, R <= 4, per-point coefficients) and "lz=".  rows=2, 4
+ *            and nbp=1 need nx % 4 == 0.  E.g. "k=4,ly=256" (2D),
+ *            "k=2,wl=32,nw=16,lz=64", "k=1,rows=1,nbp=1,lz=128",
+ *            "k=1,rows=1,nbp=0,lz=32,lpr=16" (3D).  Unknown keys or
+ *            infeasible values give EINVAL.
  */
 STENCIL_API int stencil_plan_ex(stencil_plan_t *plan, int ndim, const int64_t *dims, int radius,
                     const float *coeffs, int ncoeffs, int boundary, int storage,

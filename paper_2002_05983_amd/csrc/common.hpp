@@ -55,6 +55,25 @@ __device__ __forceinline__ float from_upper_lane(float v, float edge) {
                                                                  __builtin_bit_cast(int, v), 0x130,
                                                                  0xf, 0xf, false));
 }
+// The same shifts within each row of L lanes: L = 64 is the whole-wavefront
+// shift above; L = 16 shifts inside every 16-lane DPP row (row_shr:1 /
+// row_shl:1), and the first (last) lane of each row gets `edge`.
+template <int L>
+__device__ __forceinline__ float from_lower_lane_in(float v, float edge) {
+    static_assert(L == 64 || L == 16, "rows of 64 or 16 lanes");
+    if constexpr (L == 64) return from_lower_lane(v, edge);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x111,
+                                                                 0xf, 0xf, false));
+}
+template <int L>
+__device__ __forceinline__ float from_upper_lane_in(float v, float edge) {
+    static_assert(L == 64 || L == 16, "rows of 64 or 16 lanes");
+    if constexpr (L == 64) return from_upper_lane(v, edge);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x101,
+                                                                 0xf, 0xf, false));
+}
 // The same shifts where the lane with no source may receive anything (zero).
 __device__ __forceinline__ float from_lower_lane_or_zero(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf,

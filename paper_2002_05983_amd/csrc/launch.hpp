@@ -61,6 +61,7 @@ struct Star3DArgs {
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
     int rows = 0; // LDS-free single-step layout: grid rows per wavefront (1, 2), 0 = xy tiles
     bool nbp = false;  // rows layout: neighbour rows loaded one plane ahead
+    int lpr = 64;      // rows layout: lanes per grid row, 64 or 16 (narrow grids, R <= 4)
     int pad = 0;  // padded-halo boundary: width of the fixed frame (0 = clamp)
     bool sym = false;  // shared coefficients per axis and distance (row layout, R <= 4)
     Coefs cf;

@@ -175,7 +175,9 @@ Pass model_3r(const stencil_plan_s *p) {
     const int R = p->radius;
     const double nx = (double)p->nx, ny = (double)p->ny, nz = (double)p->nz;
     const double lz = std::min<double>(p->s3_lz, nz);
-    const double nstrips = std::ceil(nx / 256.0), nyb = std::ceil(ny / p->s3_rpl);
+    // a wavefront holds 64 / lpr row groups of lpr lanes (4 cells each)
+    const double groups = 64.0 / p->s3_lpr;
+    const double nstrips = std::ceil(nx / (4.0 * p->s3_lpr)), nyb = std::ceil(ny / (p->s3_rpl * groups));
     const double nseg = std::ceil(nz / lz);
     const double waves = nstrips * nyb * nseg;
     const double per_row = 4.0 * (6.0 * R + 1.0) + 2.0 * R + kRow3R;

@@ -123,6 +123,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         p->s3_pair = 0;
         p->s3_rpl = 0;
         p->s3_nbp = 0;
+        p->s3_lpr = 64;
         // Above radius 4 the xy-tile kernel's z-queue of 2R+1 planes no
         // longer fits a 1024-thread workgroup's 128 VGPRs (it spills) and 2R
         // of its 32 tile rows are halo; the LDS-free row layout keeps every
@@ -152,6 +153,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
     if (tune && *tune) {
         std::string s(tune);
         size_t pos = 0;
+        bool rows_set = false, nbp_set = false;
         while (pos <= s.size()) {
             size_t comma = s.find(',', pos);
             if (comma == std::string::npos) comma = s.size();
@@ -162,6 +164,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 p->variant = STAR_NAIVE;
                 p->K = 1;
                 p->s3_rpl = p->s3_nbp = 0;
+                p->s3_lpr = 64;
                 continue;
             }
             size_t eq = item.find('=');
@@ -170,6 +173,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             std::string key = item.substr(0, eq), val = item.substr(eq + 1);
             if (key == "nbp" && p->ndim == 3 && (val == "0" || val == "1")) {
                 p->s3_nbp = val == "1";
+                nbp_set = true;
                 p->variant = STAR_S3D;
                 continue;
             }
@@ -178,7 +182,10 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 return star_set_error(STENCIL_EINVAL, ("bad tune value '" + item + "'").c_str());
             if (key == "k") {
                 p->K = v;
-                if (v != 1) p->s3_rpl = p->s3_nbp = 0;  // the row layout is single-step
+                if (v != 1) {  // the row layout is single-step
+                    p->s3_rpl = p->s3_nbp = 0;
+                    p->s3_lpr = 64;
+                }
             } else if (key == "ly" && p->ndim == 2) {
                 p->ly = v;
             } else if (key == "lz" && p->ndim == 3) {
@@ -187,27 +194,42 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
             } else if (key == "nw" && p->ndim == 3) {
                 p->s3_rows = v;
                 p->s3_rpl = p->s3_nbp = 0;  // an xy-tile key selects the xy-tile kernel
+                p->s3_lpr = 64;
                 p->variant = STAR_S3D;
             } else if (key == "vec" && p->ndim == 3) {
                 p->vec = v;
                 p->s3_rpl = p->s3_nbp = 0;
+                p->s3_lpr = 64;
                 p->variant = STAR_S3D;
             } else if (key == "wl" && p->ndim == 3) {
                 p->s3_lanes = v;
                 p->s3_rpl = p->s3_nbp = 0;
+                p->s3_lpr = 64;
                 p->variant = STAR_S3D;
             } else if (key == "rows" && p->ndim == 3) {
                 p->s3_rpl = v;
+                rows_set = true;
+                p->variant = STAR_S3D;
+            } else if (key == "lpr" && p->ndim == 3) {
+                if (v != 64 && v != 16) return star_set_error(STENCIL_EINVAL, "lpr must be 64 or 16");
+                p->s3_lpr = v;
                 p->variant = STAR_S3D;
             } else if (key == "pair" && p->ndim == 3) {
                 if (v != 1) return star_set_error(STENCIL_EINVAL, "pair takes the value 1");
                 p->s3_pair = 1;
                 p->s3_rpl = p->s3_nbp = 0;
+                p->s3_lpr = 64;
                 p->variant = STAR_S3D;
 
             } else {
                 return star_set_error(STENCIL_EINVAL, ("unknown tune key '" + key + "'").c_str());
             }
+        }
+        // 16 lanes per row select the row layout with one row per lane
+        // group and no neighbour prefetch, unless rows= / nbp= say otherwise
+        if (p->s3_lpr == 16 && p->variant == STAR_S3D) {
+            if (!rows_set) p->s3_rpl = 1;
+            if (!nbp_set) p->s3_nbp = 0;
         }
     }
     if (p->variant == STAR_S2D) {
@@ -254,11 +276,15 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
                 return star_set_error(STENCIL_EINVAL, "shared coefficients run one row per wavefront");
             if ((p->s3_rpl > 1 || p->s3_nbp) && p->nx % 4 != 0)
                 return star_set_error(STENCIL_EINVAL, "rows=2, 4 and nbp=1 need rows of 16 bytes (nx % 4 == 0)");
+            if (p->s3_lpr == 16 && (p->s3_rpl != 1 || p->s3_nbp || R > 4 || p->sym))
+                return star_set_error(STENCIL_EINVAL,
+                                      "lpr=16 runs one row per lane group (rows=1, nbp=0), R <= 4, "
+                                      "per-point coefficients");
             if (p->s3_lz == 0) p->s3_lz = default_lz_rows(p);
             if (p->s3_lz < 1) return star_set_error(STENCIL_EINVAL, "lz must be >= 1");
             p->vec = 4;
-            p->tile[0] = 256;
-            p->tile[1] = p->s3_rpl;
+            p->tile[0] = 4 * p->s3_lpr;
+            p->tile[1] = p->s3_rpl * (64 / p->s3_lpr);
             p->tile[2] = p->s3_lz;
             return STENCIL_OK;
         }
@@ -371,6 +397,7 @@ hipError_t plan_launch_pass(const stencil_plan_s *p, int k, const float *src, fl
                 // one-row form without prefetched neighbour rows
                 a.rows = a.aligned ? p->s3_rpl : 1;
                 a.nbp = a.aligned && p->s3_nbp;
+                a.lpr = p->s3_lpr;
                 switch (p->radius) {
                     case 1: return launch_star3d_rows_r1(a, stream);
                     case 2: return launch_star3d_rows_r2(a, stream);
@@ -411,8 +438,9 @@ std::string plan_describe_config(const stencil_plan_s *p) {
     char buf[256];
     const char *v = p->variant == STAR_NAIVE ? "naive" : p->variant == STAR_S2D ? "s2d" : "s3d";
     if (p->variant == STAR_S3D && p->s3_rpl > 0)
-        snprintf(buf, sizeof buf, "variant=s3d ndim=3 R=%d K=1 layout=rows rows=%d nbp=%d lz=%d by=%s",
-                 p->radius, p->s3_rpl, p->s3_nbp, p->s3_lz, p->tuned_by.c_str());
+        snprintf(buf, sizeof buf, "variant=s3d ndim=3 R=%d K=1 layout=rows rows=%d nbp=%d lz=%d%s by=%s",
+                 p->radius, p->s3_rpl, p->s3_nbp, p->s3_lz, p->s3_lpr == 16 ? " lpr=16" : "",
+                 p->tuned_by.c_str());
     else if (p->variant == STAR_S3D)
         snprintf(buf, sizeof buf,
                  "variant=%s ndim=3 R=%d K=%d tile=%dx%dx%d vec=%d wl=%d nw=%d lz=%d%s%s by=%s",

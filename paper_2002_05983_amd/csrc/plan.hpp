@@ -46,6 +46,7 @@ struct stencil_plan_s {
     int s3_pair = 0;    // 1: two planes per barrier (single-step passes)
     int s3_rpl = 0;     // > 0: LDS-free single-step layout, grid rows per wavefront
     int s3_nbp = 0;     // rows layout: neighbour rows loaded one plane ahead
+    int s3_lpr = 64;    // rows layout: lanes per grid row (64, or 16 for narrow grids)
     std::string tuned_by = "default";
 };
 

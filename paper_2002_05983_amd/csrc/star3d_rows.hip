@@ -13,7 +13,6 @@ namespace star {
 namespace {
 
 using s3r::prefetch_rows3;
-using s3r::STRIP;
 using s3r::star3d_rows_body;
 
 // Four wavefronts per workgroup, each independent.  Wavefront w takes strip
@@ -22,7 +21,9 @@ using s3r::star3d_rows_body;
 // XCD-aware block order, one L2) hold neighbouring strips and row blocks
 // at the same planes, so the y-neighbour rows they load from each other
 // are cache hits.  WPE: waves per SIMD the register budget is sized for.
-template <int R, int RPL, bool NBP, bool AL, int WPE, bool SYM>
+// LPR: lanes per grid row (64, or 16: four rows of a 64-column strip per
+// wavefront, for narrow grids).
+template <int R, int RPL, bool NBP, bool AL, int WPE, bool SYM, int LPR>
 __global__ __launch_bounds__(256, WPE) void star3d_rows(const float *__restrict__ src,
                                                         float *__restrict__ dst, int nx, int ny,
                                                         int nz, int nstrips, int nyb, int lz,
@@ -34,18 +35,20 @@ __global__ __launch_bounds__(256, WPE) void star3d_rows(const float *__restrict_
     const int yb = (wave / nstrips) % nyb;
     const int zseg = wave / (nstrips * nyb);
     constexpr int D = prefetch_rows3<R, RPL>();
-    if (AL && (strip + 1) * STRIP > nx)
-        star3d_rows_body<R, RPL, D, NBP, AL, true, SYM>(src, dst, nx, ny, nz, strip, yb * RPL,
-                                                        zseg * lz, lz, cf, pad);
+    constexpr int RPW = RPL * (64 / LPR);  // grid rows per wavefront
+    if (AL && (strip + 1) * LPR * 4 > nx)
+        star3d_rows_body<R, RPL, D, NBP, AL, true, SYM, LPR>(src, dst, nx, ny, nz, strip, yb * RPW,
+                                                             zseg * lz, lz, cf, pad);
     else
-        star3d_rows_body<R, RPL, D, NBP, AL, false, SYM>(src, dst, nx, ny, nz, strip, yb * RPL,
-                                                         zseg * lz, lz, cf, pad);
+        star3d_rows_body<R, RPL, D, NBP, AL, false, SYM, LPR>(src, dst, nx, ny, nz, strip, yb * RPW,
+                                                              zseg * lz, lz, cf, pad);
 }
 
-template <int RPL, bool NBP, bool AL, bool SYM = false>
+template <int RPL, bool NBP, bool AL, bool SYM = false, int LPR = 64>
 hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
-    const int nstrips = (a.nx + STRIP - 1) / STRIP;
-    const int nyb = (a.ny + RPL - 1) / RPL;
+    constexpr int SW = LPR * 4, RPW = RPL * (64 / LPR);
+    const int nstrips = (a.nx + SW - 1) / SW;
+    const int nyb = (a.ny + RPW - 1) / RPW;
     const int nseg = (a.nz + a.lz - 1) / a.lz;
     const int64_t nwaves = (int64_t)nstrips * nyb * nseg;
     if (nwaves > ((int64_t)1 << 30)) return hipErrorInvalidValue;
@@ -56,7 +59,7 @@ hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
     constexpr int R = STAR_R;
     constexpr int WPE = (RPL == 1 && (R <= 3 || (R == 4 && AL && !NBP))) ? 4 : 2;
     const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-    hipLaunchKernelGGL((star3d_rows<STAR_R, RPL, NBP, AL, WPE, SYM>), dim3(blocks), dim3(256), 0,
+    hipLaunchKernelGGL((star3d_rows<STAR_R, RPL, NBP, AL, WPE, SYM, LPR>), dim3(blocks), dim3(256), 0,
                        stream, a.src, a.dst, a.nx, a.ny, a.nz, nstrips, nyb, a.lz, (int)nwaves,
                        a.pad, a.cf);
     return hipGetLastError();
@@ -69,6 +72,16 @@ hipError_t launch_rows(const Star3DArgs &a, hipStream_t stream) {
 
 hipError_t STAR_CAT(launch_star3d_rows_r, STAR_R)(const Star3DArgs &a, hipStream_t stream) {
     if (a.lz < 1 || a.nx < 1 || a.ny < 1 || a.nz < 1 || a.K != 1) return hipErrorInvalidValue;
+    if (a.lpr == 16) {
+        // 16 lanes per row: one row per group, no prefetch, per-point coefficients
+        if constexpr (STAR_R <= 4) {
+            if (a.rows != 1 || a.nbp || a.sym) return hipErrorInvalidValue;
+            return a.aligned ? launch_rows<1, false, true, false, 16>(a, stream)
+                             : launch_rows<1, false, false, false, 16>(a, stream);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (a.lpr != 64) return hipErrorInvalidValue;
     if (a.sym) {
         // shared coefficients: one row per wavefront, radius <= 4
         if constexpr (STAR_R <= 4) {

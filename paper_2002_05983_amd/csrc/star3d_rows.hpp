@@ -19,6 +19,11 @@
 //     wave shifts; the lanes at the strip's ends take the cells beyond the
 //     strip from a halo of up to 8 cells per side that only those two
 //     lanes load (the DPP "old" operand of the lane with no source).
+//   * Narrow grids (LPR = 16 lanes per row): the wavefront is split into
+//     four 16-lane row groups, each owning one grid row of a 64-column
+//     strip (four consecutive rows per wavefront); x-shifts stay inside
+//     each 16-lane DPP row, and each group's end lanes load its halo.
+//     Grids a few dozen cells wide then keep most lanes busy.
 //   * Wavefronts are independent: no LDS, no barrier; latency is hidden by
 //     the other wavefronts on the SIMD.
 //   * Clamp boundary (Sec. III.B): plane and row indices are clamped when
@@ -38,10 +43,13 @@ namespace star {
 namespace s3r {
 
 constexpr int VEC = 4;
-constexpr int STRIP = 64 * VEC;  // columns per wavefront strip
+constexpr int STRIP = 64 * VEC;  // columns per wavefront strip (64 lanes per row)
 
 // One wavefront's work: `rows0` .. rows0+RPL-1 of strip `strip`, planes
 // z0 .. min(z0+lz, nz)-1.  Every argument is wave-uniform.
+// LPR: lanes per row, 64 (one row group, strips of 256 columns) or 16
+// (four row groups, strips of 64 columns; group g owns rows
+// rows0 + g*RPL ..; one row per group, radius <= 4, no neighbour prefetch).
 // NBP: the y-neighbour rows and the halo of the next centre plane are
 // loaded one plane ahead (more registers, latency off the critical path).
 // SYM: shared coefficients, one per axis and distance (cf holds c_C, then
@@ -49,7 +57,8 @@ constexpr int STRIP = 64 * VEC;  // columns per wavefront strip
 // rounded sum of the pair of cells.
 // pad > 0: padded-halo boundary (Sec. IV.B): the grid is the padded array
 // and the cells of its frame of `pad` cells keep their values.
-template <int R, int RPL, int D, bool NBP, bool ALIGNED, bool RAGGED, bool SYM = false>
+template <int R, int RPL, int D, bool NBP, bool ALIGNED, bool RAGGED, bool SYM = false,
+          int LPR = 64>
 __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
                                                  float *__restrict__ dst, int nx, int ny, int nz,
                                                  int strip, int rows0, int z0, int lz,
@@ -59,10 +68,15 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
     constexpr int HW = R > 4 ? 8 : 4;  // halo cells per side
     constexpr int NB = NBP ? 2 : 1;    // neighbour buffers (current, next)
     static_assert(R <= 2 * VEC, "x-neighbours come from the lanes at most two away");
+    static_assert(LPR == 64 || (LPR == 16 && RPL == 1 && R <= VEC && !NBP),
+                  "16-lane rows: one row per group, radius <= 4, no neighbour prefetch");
+    constexpr int SW = LPR * VEC;      // strip width in columns
 
     const int lane = threadIdx.x & 63;
-    const int x0 = strip * STRIP;
-    const int col0 = x0 + lane * VEC;
+    const int gl = lane & (LPR - 1);   // lane within its row group
+    const int y0 = LPR == 64 ? rows0 : rows0 + (lane / LPR) * RPL;  // the group's first row
+    const int x0 = strip * SW;
+    const int col0 = x0 + gl * VEC;
     const int z1 = min(z0 + lz, nz);
     const int zstart = z0 - R;          // first plane streamed
     const int niter = (z1 - z0) + 2 * R;
@@ -70,7 +84,7 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
     const size_t plane = (size_t)nx * (size_t)ny;
     const int plane_bytes = (int)(plane * sizeof(float));  // < 2^31, checked by the launcher
     const bool first_strip = x0 == 0;
-    const bool last_strip = x0 + STRIP >= nx;
+    const bool last_strip = x0 + SW >= nx;
 
     // Row `yy` (clamped to the grid) of plane `zz` (clamped), this lane's 4 cells.
     auto load_row = [&](int zz, int yy, float (&v)[VEC]) STAR_INLINE {
@@ -94,18 +108,18 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
         }
     };
 
-    // Halo cells of row yy, plane zz, held by the strip's two end lanes in
-    // one register set: lane 0 gets columns x0-HW .. x0-1 (the cells left of
-    // the strip), lane 63 columns x0+STRIP .. x0+STRIP+HW-1 (right of it);
+    // Halo cells of row yy, plane zz, held by the row group's two end lanes
+    // in one register set: its first lane gets columns x0-HW .. x0-1 (the
+    // cells left of the strip), its last lane x0+SW .. x0+SW+HW-1 (right of it);
     // other lanes' values are never read.  The first strip's left halo and
     // the last strip's right halo are the border column, which the end lane
     // holds itself (filled in at use).
     auto load_halo = [&](int zz, int yy, float (&h)[HW]) STAR_INLINE {
         const float *row = src + (size_t)clampi(zz, nz) * plane + (size_t)clampi(yy, ny) * nx;
-        if ((lane == 0 && !first_strip) || (lane == 63 && !last_strip)) {
-            const int c0 = lane == 0 ? x0 - HW : x0 + STRIP;
+        if ((gl == 0 && !first_strip) || (gl == LPR - 1 && !last_strip)) {
+            const int c0 = gl == 0 ? x0 - HW : x0 + SW;
             if constexpr (ALIGNED) {
-                // 16-byte columns: x0 - HW >= 0 and x0 + STRIP <= nx - 4 here
+                // 16-byte columns: x0 - HW >= 0 and x0 + SW <= nx - 4 here
 #pragma unroll
                 for (int c = 0; c < HW / VEC; ++c) {
                     const float4 t = *reinterpret_cast<const float4 *>(row + min(c0 + VEC * c, nx - VEC));
@@ -113,7 +127,7 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
                 }
                 if constexpr (HW > VEC) {
                     // the second vector of the right halo may lie beyond nx
-                    if (lane == 63 && c0 + VEC >= nx) {
+                    if (gl == LPR - 1 && c0 + VEC >= nx) {
 #pragma unroll
                         for (int j = VEC; j < HW; ++j) h[j] = h[VEC - 1];
                     }
@@ -126,7 +140,7 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
     };
 
     float q[NQ][RPL][VEC];           // own rows, ring of planes
-    float nb[NB][2 * R][VEC];        // rows rows0-R .. rows0-1, rows0+RPL .. rows0+RPL+R-1
+    float nb[NB][2 * R][VEC];        // rows y0-R .. y0-1, y0+RPL .. y0+RPL+R-1
     float h[NB][RPL][HW];            // halo of each own row (end lanes only)
 #pragma unroll
     for (int p = 0; p < NQ; ++p)
@@ -143,18 +157,18 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
 
     auto load_plane = [&](int zz, float (&v)[RPL][VEC]) STAR_INLINE {
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) load_row(min(zz, zlast), rows0 + k, v[k]);
+        for (int k = 0; k < RPL; ++k) load_row(min(zz, zlast), y0 + k, v[k]);
     };
     // y-neighbour rows and halo of centre plane zc into buffer B
     auto load_centre = [&](int zc, auto bc) STAR_INLINE {
         constexpr int B = decltype(bc)::value;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            load_row(zc, rows0 - R + j, nb[B][j]);
-            load_row(zc, rows0 + RPL + j, nb[B][R + j]);
+            load_row(zc, y0 - R + j, nb[B][j]);
+            load_row(zc, y0 + RPL + j, nb[B][R + j]);
         }
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) load_halo(zc, rows0 + k, h[B][k]);
+        for (int k = 0; k < RPL; ++k) load_halo(zc, y0 + k, h[B][k]);
     };
 
     static_for<0, D>([&](auto phc) STAR_INLINE {
@@ -181,8 +195,8 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
 #pragma unroll
         for (int m = 1; m <= R; ++m) {
             if (m <= VEC) {
-                left[m] = from_lower_lane(c[VEC - m], hlk[HW - m]);
-                right[m] = from_upper_lane(c[m - 1], hrk[m - 1]);
+                left[m] = from_lower_lane_in<LPR>(c[VEC - m], hlk[HW - m]);
+                right[m] = from_upper_lane_in<LPR>(c[m - 1], hrk[m - 1]);
             } else {  // two lanes away: lane 1 takes lane 0's halo via the first shift
                 left[m] = from_lower_lane(from_lower_lane(c[2 * VEC - m], hlk[HW + VEC - m]),
                                           hlk[HW - m]);
@@ -230,13 +244,13 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
     // Padded-halo frame: a frame cell (element e of own row k, plane r)
     // keeps its centre value ctr; other cells keep v.
     auto frame_value = [&](int r, int k, int e, float ctr, float v) STAR_INLINE -> float {
-        const int yy = rows0 + k, cc = col0 + e;
+        const int yy = y0 + k, cc = col0 + e;
         return (r < pad || r >= nz - pad || yy < pad || yy >= ny - pad || cc < pad ||
                 cc >= nx - pad) ? ctr : v;
     };
 
     auto store_row = [&](int r, int k, const float (&res)[VEC]) STAR_INLINE {
-        const int yy = rows0 + k;
+        const int yy = y0 + k;
         const bool ok_row = yy < ny && r >= z0 && r < z1;
         const auto rs = buffer_rsrc(dst + (size_t)clampi(r, nz) * plane, plane_bytes);
         const int rowoff = clampi(yy, ny) * nx;

@@ -78,6 +78,16 @@ std::vector<std::string> candidates(const stencil_plan_s *p) {
                         out.push_back(buf);
                     }
                 }
+            // 16 lanes per row (four rows of a 64-column strip per
+            // wavefront): only narrow grids gain (measured with 256 planes
+            // of 256 rows: +12 % at nx = 64, R = 3, 4; the xy tiles lead
+            // from nx = 96)
+            if (R <= 4 && !p->sym && p->nx <= 128)
+                for (int lz : {32, 64, 128, 256}) {
+                    if (lz > p->nz && lz != 32) continue;
+                    snprintf(buf, sizeof buf, "k=1,rows=1,nbp=0,lz=%d,lpr=16", lz);
+                    out.push_back(buf);
+                }
         }
         // shared coefficients in 3D run the row layout only
         const int kmax = p->sym ? 0 : p->storage == STENCIL_F32 ? max_k3d(R) : 1;

@@ -175,6 +175,13 @@ def test_batch_entry_points_reject_null(lib):
     (3, [63, 64, 64], 2, b"k=1,rows=1,nbp=0", True),
     (3, [64, 64, 64], 2, b"k=2,rows=1", False),          # single-step layout
     (3, [64, 64, 64], 2, b"k=1,rows=3", False),
+    (3, [64, 64, 64], 4, b"k=1,lz=16,lpr=16", True),       # 16 lanes per row, 16-byte rows ...
+    (3, [63, 64, 64], 4, b"k=1,rows=1,nbp=0,lpr=16", True),  # ... or not
+    (3, [64, 64, 64], 5, b"k=1,lpr=16", False),             # radius <= 4
+    (3, [64, 64, 64], 2, b"k=1,rows=2,lpr=16", False),      # one row per lane group
+    (3, [64, 64, 64], 2, b"k=1,nbp=1,lpr=16", False),       # no neighbour prefetch
+    (3, [64, 64, 64], 2, b"k=1,lpr=32", False),
+    (3, [64, 64, 64], 2, b"k=2,lpr=16", False),             # single-step layout
     (3, [64, 64, 64], 2, b"k=1,nbp=2", False),
     (3, [64, 64, 64], 1, b"k=2,bogus=3", False),
     (3, [64, 64, 64], 1, b"k=x", False),
@@ -246,6 +253,7 @@ def _plan_sym(lib, ndim, dims, radius, coeffs, boundary=0, tune=None):
     (3, 2, 7, 0, b"k=1,wl=32,nw=16", (-1,)),
     (3, 2, 7, 0, b"k=1,rows=1,nbp=1,lz=64", (0, -3)),
     (3, 2, 7, 0, b"k=1,rows=2", (-1,)),
+    (3, 2, 7, 0, b"k=1,rows=1,lpr=16", (-1,)),  # 16 lanes per row: per-point coefficients
 ])
 def test_symmetric_plan_validation(lib, ndim, radius, ncoef, boundary, tune, want):
     rc, h = _plan_sym(lib, ndim, [64] * ndim, radius, [0.1] * ncoef, boundary, tune)

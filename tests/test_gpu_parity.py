@@ -157,8 +157,8 @@ S3R_SHAPES = [(1, 1, 1), (3, 2, 5), (9, 17, 33), (20, 37, 300), (7, 33, 600), (1
 def test_s3d_rows_layout_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
     """The LDS-free single-step layout: one, two and four rows per
     wavefront (two above radius 4, four up to it), with and without
-    prefetched neighbour rows, segments shorter and longer than the grid,
-    several passes."""
+    prefetched neighbour rows, 16 lanes per row up to radius 4, segments
+    shorter and longer than the grid, several passes."""
     c = synth.coefficients(720 + radius, 3, radius)
     f = synth.grid_uniform(820 + radius, shape)
     want = oracle_mod.star_run_f32(f, c, radius, 3)
@@ -176,6 +176,12 @@ def test_s3d_rows_layout_matches_oracle_bitwise(torch, st, oracle_mod, radius, s
                 got, desc = gpu_run(torch, st, f, radius, c, 3, tune=tune)
                 assert "layout=rows" in desc, desc
                 assert_bitwise(got, want, f"s3d rows {shape} r{radius} [{desc}]")
+    if radius <= 4:
+        # 16 lanes per row: four rows of a 64-column strip per wavefront
+        for lz in (1, 4, 64):
+            got, desc = gpu_run(torch, st, f, radius, c, 3, tune=f"k=1,rows=1,nbp=0,lz={lz},lpr=16")
+            assert "lpr=16" in desc, desc
+            assert_bitwise(got, want, f"s3d rows lpr=16 {shape} r{radius} [{desc}]")
 
 
 @pytest.mark.parametrize("radius", [1, 2, 3, 4])
@@ -473,6 +479,13 @@ def test_model_predictions_and_errors(torch, st):
     assert m3["GCell/s"] > 0 and m3["plane_us"] > 0
     m3r = p3.model("k=1,rows=1,lz=64")  # the LDS-free layout has no plane latency term
     assert m3r["GCell/s"] > 0 and m3r["hbm_us"] > 0 and m3r["plane_us"] == 0
+    # a 64-wide grid fills a quarter of a 256-column strip; four 16-lane
+    # rows per wavefront issue a quarter of the wavefronts for the same bytes
+    p64 = st.Plan((64, 64, 64), 3, synth.coefficients(6, 3, 3))
+    wide, narrow = p64.model("k=1,rows=1,lz=64"), p64.model("k=1,rows=1,lz=64,lpr=16")
+    assert narrow["valu_us"] == pytest.approx(wide["valu_us"] / 4)
+    assert narrow["hbm_us"] == pytest.approx(wide["hbm_us"])
+    p64.close()
     pn = st.Plan((64, 64), 1, synth.coefficients(5, 2, 1), tune="naive")
     with pytest.raises(st.StencilError):
         pn.model()
