@@ -129,7 +129,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         // of its 32 tile rows are halo; the LDS-free row layout keeps every
         // cell an output cell.
         // From radius 5 on the row layout leads (512^3, two rows per
-        // wavefront: 386, 346, 317, 283 GCell/s at R = 5..8 against at most
+        // wavefront: 399, 360, 330, 291 GCell/s at R = 5..8 against at most
         // 358, 201, 76, 45 for the tile kernel); unaligned rows take one row
         if (R >= 5 && p->storage == STENCIL_F32) {
             p->s3_rpl = p->nx % 4 == 0 ? 2 : 1;

@@ -15,12 +15,16 @@ namespace {
 using s3r::prefetch_rows3;
 using s3r::star3d_rows_body;
 
-// Four wavefronts per workgroup, each independent.  Wavefront w takes strip
-// w % nstrips of row block (w / nstrips) % nyb and z-segment w / (nstrips *
-// nyb): consecutive wavefronts (one workgroup, one CU; and, through the
-// XCD-aware block order, one L2) hold neighbouring strips and row blocks
-// at the same planes, so the y-neighbour rows they load from each other
-// are cache hits.  WPE: waves per SIMD the register budget is sized for.
+// Four wavefronts per workgroup, each independent.  Up to radius 4
+// wavefront w takes strip w % nstrips of row block (w / nstrips) % nyb and
+// z-segment w / (nstrips * nyb); above radius 4 the row block runs fastest
+// (row block w % nyb of strip (w / nyb) % nstrips).  Either way consecutive
+// wavefronts (one workgroup, one CU; and, through the XCD-aware block
+// order, one L2) hold neighbouring rows at the same planes, so the
+// y-neighbour rows they load from each other are cache hits; strip-first
+// also keeps the halo columns of adjacent strips together (measured on
+// 512^3, row block first: R = 1, 2 -11 and -7 %, R = 3, 4 -1 %, R = 5, 6,
+// 8 +3, +3, +4 %).  WPE: waves per SIMD the register budget is sized for.
 // LPR: lanes per grid row (64, or 16: four rows of a 64-column strip per
 // wavefront, for narrow grids).
 template <int R, int RPL, bool NBP, bool AL, int WPE, bool SYM, int LPR>
@@ -31,8 +35,9 @@ __global__ __launch_bounds__(256, WPE) void star3d_rows(const float *__restrict_
     const int wave = xcd_logical_block(blockIdx.x, gridDim.x) * 4 +
                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
-    const int strip = wave % nstrips;
-    const int yb = (wave / nstrips) % nyb;
+    constexpr bool YFIRST = R > 4;
+    const int yb = YFIRST ? wave % nyb : (wave / nstrips) % nyb;
+    const int strip = YFIRST ? (wave / nyb) % nstrips : wave % nstrips;
     const int zseg = wave / (nstrips * nyb);
     constexpr int D = prefetch_rows3<R, RPL>();
     constexpr int RPW = RPL * (64 / LPR);  // grid rows per wavefront
