@@ -184,6 +184,28 @@ def test_s3d_rows_layout_matches_oracle_bitwise(torch, st, oracle_mod, radius, s
             assert_bitwise(got, want, f"s3d rows lpr=16 {shape} r{radius} [{desc}]")
 
 
+@pytest.mark.parametrize("radius", [2, 4])
+def test_autotune_times_narrow_rows_only_on_narrow_grids(torch, st, oracle_mod, radius, monkeypatch):
+    """Grids at most 128 cells wide are also timed with four 16-lane rows
+    per wavefront; whatever the autotuner keeps is bitwise exact, and wider
+    grids do not time that form."""
+    monkeypatch.delenv("STENCIL_TUNE_CACHE", raising=False)
+    monkeypatch.delenv("STENCIL_TUNE_TOP", raising=False)
+    c = synth.coefficients(990 + radius, 3, radius)
+    for shape, narrow in (((40, 33, 61), True), ((24, 20, 300), False)):
+        f = synth.grid_uniform(991, shape)
+        x = torch.from_numpy(f).cuda()
+        y = torch.empty_like(x)
+        plan = st.Plan(shape, radius, c)
+        timed = [cfg for cfg, _ in plan.autotune(x, y)]
+        assert any("lpr=16" in cfg for cfg in timed) == narrow, timed
+        plan.run(x, y, 3)
+        torch.cuda.synchronize()
+        assert_bitwise(y.cpu().numpy(), oracle_mod.star_run_f32(f, c, radius, 3),
+                       f"autotuned {shape} r{radius} [{plan.describe()}]")
+        plan.close()
+
+
 @pytest.mark.parametrize("radius", [1, 2, 3, 4])
 def test_s3d_default_config_vs_fp64(torch, st, oracle_mod, radius):
     shape = (40, 45, 130)
