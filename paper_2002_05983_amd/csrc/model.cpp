@@ -187,8 +187,8 @@ Pass model_3r(const stencil_plan_s *p) {
     const double cells = nx * ny * nz;
     // the 2R neighbour rows of each centre plane come from L2 when the
     // neighbouring wavefronts loaded them moments before; the fraction that
-    // misses grows with R (FETCH_SIZE on 512^3: 2.2-3.1x the algorithmic
-    // reads at R = 3, 4; near 1x at R = 1)
+    // misses grows with R (FETCH_SIZE on 512^3: 1.16x the algorithmic
+    // reads at R = 1, 2.1-2.4x from R = 3 on with 2 or 4 rows per wavefront)
     const double miss = std::min(kMissMax, kMissSlope * (R - 1));
     const double reads = (lz + 2.0 * R) / lz * (1.0 + 2.0 * R * miss / p->s3_rpl);
     s.t_hbm = (cells * 4.0 * reads + cells * 4.0) / kHbmEff3D;
