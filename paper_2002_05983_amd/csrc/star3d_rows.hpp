@@ -316,7 +316,9 @@ __device__ __forceinline__ void star3d_rows_body(const float *__restrict__ src,
 // R <= 2; from R = 3 on one plane, which shortens the time between a
 // wavefront loading its own row and its neighbours reading that row back
 // from L2 (512^3, R = 3, two rows per wavefront: 530 -> 547 GCell/s; equal
-// elsewhere).
+// elsewhere).  Two planes from R = 3 on: four rows per wavefront at R = 3, 4
+// 555 -> 546 and 525 -> 513 (and 12 bytes of scratch per lane at R = 4),
+// two rows at R = 5, 6 402 -> 399 and 365 -> 359 GCell/s.
 template <int R, int RPL>
 constexpr int prefetch_rows3() {
     return R <= 2 ? (RPL == 1 ? 6 : 3) : 1;
