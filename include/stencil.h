@@ -155,7 +155,7 @@ STENCIL_API int stencil_coeffs_per_direction(int ndim, int radius, const float *
  *            for F32.
  *   tune     NULL for automatic selection, or a configuration string of
  *            comma-separated items: "naive" (one thread per cell, one step
- *            per launch); 2D "k=" (fused steps, K*R <= 16, at most 8) and
+ *            per launch); 2D "k=" (fused steps, K*R <= 16, at most 10) and
  *            "ly=" (rows per segment); 3D "k=" (at most 4 for R = 1, 3 for
  *            R = 2, 3, 2 for R = 4..6, 1 for R = 7, 8),
  *            "wl=" (lanes per tile row, 32 or 64), "vec=" (cells per lane,

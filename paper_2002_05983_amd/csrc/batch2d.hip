@@ -62,6 +62,8 @@ const void *pick(const BatchLaunchArgs &a) {
         case 6: return pick_al<6>(a.aligned);
         case 7: return pick_al<7>(a.aligned);
         case 8: return pick_al<8>(a.aligned);
+        case 9: return pick_al<9>(a.aligned);
+        case 10: return pick_al<10>(a.aligned);
         default: return nullptr;
     }
 }

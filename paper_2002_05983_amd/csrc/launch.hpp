@@ -18,19 +18,21 @@ struct Star2DArgs {
     const float *src;
     float *dst;
     int nx, ny;
-    int K;        // steps fused in this pass (1..kMaxK2D)
+    int K;        // steps fused in this pass (1..max_k2d(R))
     int ly;       // output rows per y-segment
     bool aligned; // nx % 4 == 0 and both grids 16-byte aligned
     int pad = 0;  // padded-halo boundary: width of the fixed frame (0 = clamp)
     bool sym = false;  // shared coefficients per axis and distance (R <= 4, K <= 4)
     Coefs cf;
 };
-constexpr int kMaxK2D = 8;
+constexpr int kMaxK2D = 10;
 // Shared coefficients (one per axis and distance) are built into the 2D
 // streaming kernel for R <= 4 and K <= kMaxKSym2D fused steps.
 constexpr int kMaxKSym2D = 4;
 // Largest K built per radius: K*R <= 16 keeps the unrolled queue code and
-// its registers in budget (K = 8, 8, 5, 4, 3, 2, 2, 2 for R = 1..8).
+// its registers in budget (K = 10, 8, 5, 4, 3, 2, 2, 2 for R = 1..8; at
+// R = 1, K = 12 needs 172 VGPRs, two wavefronts per SIMD, and is slower
+// than K = 10: 4045 against 4670 GCell/s on 16384^2).
 constexpr int max_k2d(int R) { return 16 / R < kMaxK2D ? 16 / R : kMaxK2D; }
 constexpr int kVec2D = 4;
 // Output columns of one strip: a wavefront spans 64*4 columns, minus the

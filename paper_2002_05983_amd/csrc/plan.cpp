@@ -21,7 +21,7 @@ constexpr int64_t kTargetWaves2D = 4096;
 // the autotuner's picks there.
 int default_k2d(int R) {
     switch (R) {
-        case 1: return 8;
+        case 1: return 10;
         case 2: return 6;
         case 3: return 4;
         case 4: return 3;
@@ -238,7 +238,7 @@ static int plan_apply(stencil_plan_s *p, const char *tune) {
         if (p->nx * 4 >= ((int64_t)1 << 31))
             return star_set_error(STENCIL_EUNSUPPORTED, "2D rows must stay below 2^31 bytes");
         if (p->K < 1 || p->K > max_k2d(R))
-            return star_set_error(STENCIL_EINVAL, "2D k must be in 1..16/R (at most 8)");
+            return star_set_error(STENCIL_EINVAL, "2D k must be in 1..16/R (at most 10)");
         if (p->sym && p->K > kMaxKSym2D)
             return star_set_error(STENCIL_EINVAL, "shared coefficients: 2D k must be 1..4");
         if (p->ly == 0) p->ly = default_ly(p, p->K);

@@ -78,6 +78,8 @@ hipError_t STAR_CAT(launch_star2d_r, STAR_R)(const Star2DArgs &a, hipStream_t st
         case 6: return launch_al<6>(a, stream);
         case 7: return launch_al<7>(a, stream);
         case 8: return launch_al<8>(a, stream);
+        case 9: return launch_al<9>(a, stream);
+        case 10: return launch_al<10>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -144,6 +144,8 @@ def test_batch_entry_points_reject_null(lib):
 
 @pytest.mark.parametrize("ndim,dims,radius,tune,ok", [
     (2, [64, 64], 1, b"k=8,ly=128", True),
+    (2, [64, 64], 1, b"k=10,ly=64", True),   # up to 10 fused steps at R = 1
+    (2, [64, 64], 1, b"k=11", False),
     (2, [64, 64], 4, b"k=4,ly=16", True),
     (2, [64, 64], 4, b"k=5", False),          # K*R > 16 is not built
     (2, [64, 64], 1, b"k=0", False),

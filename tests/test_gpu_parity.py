@@ -78,7 +78,7 @@ def test_s2d_matches_oracle_bitwise(torch, st, oracle_mod, radius, shape):
     c = synth.coefficients(400 + radius, 2, radius)
     f = synth.grid_uniform(500 + radius, shape)
     cache = {}
-    for K in (1, 2, 3, 4, 5, 8):
+    for K in (1, 2, 3, 4, 5, 8, 10):
         if K * radius > 16:
             continue
         for ly in (7, 32):
@@ -298,7 +298,7 @@ def test_run_rejects_overlap_and_bad_steps(torch, st):
     with pytest.raises(ValueError):
         plan.run(x, torch.empty_like(x), -1)
     with pytest.raises(ValueError):
-        st.Plan((16, 16), 1, c, tune="k=9")
+        st.Plan((16, 16), 1, c, tune="k=11")
     with pytest.raises(ValueError):
         st.Plan((16, 16), 1, c, tune="bogus=1")
 
